@@ -1,0 +1,180 @@
+"""Benchmark of the explicit bioheat stepper on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2|3]
+
+A bench step is one rfa_step call that advances the workload by its full
+simulated duration (all per-step work: conduction, perfusion, RF source,
+held voxels, float-float Euler update, Arrhenius damage and latch,
+per-step diagnostics), with the grid's inputs resident in HBM.  The default
+workload is the single-instance heterogeneous case: 128^3 voxels at 0.5 mm,
+liver with a tumour and 3-6 vessels, straight needle, 1000 steps of
+0.01 s.  --config 3 runs the 256^3 umbrella-needle case (6000 steps).
+
+Prints one JSON line: voxel-updates/s over the timed steps, the step
+kernel's roofline (algorithmic bytes per launch over its HIP-event-timed
+average duration), and the FP64 oracle timed on this host's cores on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("GVoxel-updates/s + % HBM roofline (fwd, fwd+adjoint) vs plain stepper, "
+          "ΔT≤1e-4K")
+# Minimum bytes one voxel-step must move through HBM (per step, one pass):
+# float-float state read + write (8 + 8), class byte (1), source increment
+# (4), damage integral read + write (4 + 4).
+BYTES_PER_VOXEL_STEP = 29
+HBM_PEAK_GBPS = 8000.0
+TIME_PERIOD = 16          # HIP-event-time every 16th step-kernel launch
+KERNEL_SOURCES = ("paper_1907_05709_amd/csrc/rfa_tiled.hip",
+                  "paper_1907_05709_amd/csrc/rfa_device.h",
+                  "paper_1907_05709_amd/csrc/rfa_kernels.hip")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload(config: int):
+    from paper_1907_05709_amd import workloads as W
+    if config == 2:
+        case = W.case_straight()
+        name = ("straight-needle liver/tumour/vessels 128^3 @0.5mm, 1000 x 0.01 s, "
+                "P~U(15,40) W (seed 2000)")
+    elif config == 3:
+        case = W.case_umbrella()
+        name = ("9-tine umbrella liver/tumour/vessels 256^3 @0.5mm, 6000 x 0.01 s, "
+                "60 W (seed 3000)")
+    else:
+        raise SystemExit("--config must be 2 or 3")
+    return case, name
+
+
+def traffic_record(config: int, plan: dict):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel sources and launch plan."""
+    path = os.path.join(ROOT, "profiles", f"traffic_step_config{config}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_hash") != kernel_hash() or rec.get("plan") != plan:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(case, sample_steps: int):
+    """The FP64 oracle (as is) on the host cores: sample_steps steps of the
+    same workload, with its per-step diagnostics."""
+    from oracle import oracle as O
+    O.build(force=False)
+    q = O.source(case)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    O.run(case, n_steps=sample_steps, q=q, diag=True)
+    dt = time.perf_counter() - t0
+    gvox = case.n_voxels * sample_steps / dt / 1e9
+    return {"value": gvox, "unit": "GVoxel-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sample_steps} of {case.n_steps} steps of the same workload "
+                      f"({case.shape[0]}^3), FP64 with per-step diagnostics, "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="oracle sample steps (0 = size for ~15 s)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--time-steps", type=int, default=0,
+                    help="override the workload's time steps per bench step (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1907_05709_amd import rfa
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    case, name = workload(args.config)
+    if args.time_steps > 0:
+        case.n_steps = args.time_steps
+        name += f" [profiling run: {args.time_steps} time steps per bench step]"
+    g = rfa.Grid(case.shape, case.spacing, device=False, time_kernels=TIME_PERIOD)
+    g.load_case(case)
+    if not args.no_tune:
+        g.tune(case.dt, reps=10)
+    plan = g.plan()
+    for _ in range(args.warmup):
+        g.step(case.n_steps, case.dt, diag=True)
+    g.kernel_stats()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    diag = None
+    for _ in range(args.steps):
+        diag = g.step(case.n_steps, case.dt, diag=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, launches, vsteps = g.kernel_stats()
+    copy_gbps = rfa.rfa_copy_bandwidth(1 << 30, 10)
+    g.close()
+
+    vox_updates = case.n_voxels * case.n_steps * args.steps
+    value = vox_updates / wall / 1e9
+    avg_ms = kms / launches
+    bytes_per_launch = BYTES_PER_VOXEL_STEP * case.n_voxels * plan["depth"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_record(args.config, plan)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GVoxel-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": name, "grid": list(case.shape), "time_steps": case.n_steps,
+                   "dt_s": case.dt, "state": "float-float f32 excess temperature",
+                   "plan": plan},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic, "kernel": "k_step_tiled" if plan["kernel"] == 2
+                     else "k_step_naive", "avg_launch_us": round(avg_ms * 1e3, 3),
+                     "launches_timed": launches, "bytes_per_launch": bytes_per_launch,
+                     "copy_ceiling_GBps": round(copy_gbps, 1)},
+        "diag_last_step": {k: diag[k] for k in ("t_max_C", "mono_violations", "residual_J")},
+    }
+    if not args.no_cpu:
+        steps = args.cpu_steps
+        if steps <= 0:
+            steps = max(2, min(case.n_steps, int(2.0e9 / case.n_voxels)))
+        out["cpu_baseline"] = cpu_baseline(case, steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

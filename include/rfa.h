@@ -1,0 +1,218 @@
+/*
+ * rfa.h -- C ABI of librfa.so, the MI355X (gfx950) explicit bioheat stepper
+ * for radio-frequency ablation.
+ *
+ * Method (Kath, Handels, Mastmeyer, "Robust GPU-based Virtual Reality
+ * Simulation of Radio Frequency Ablations for Various Needle Geometries and
+ * Locations"): the simplified Pennes equation, Eq. (2675-eq1_Kath),
+ *     rho c dT/dt = div(K grad T) + w_b c_b (T_a - T) + Q_m  (+ RF power q),
+ * discretised with symmetric second differences, Eq. (2675-eq3), and an
+ * explicit forward-Euler voxel update, Eq. (CUDAbioheat3d), on a voxel grid;
+ * voxels of "fixed" classes keep their value (Alg. 1, Eq. (2675-eq6)); two
+ * temperature images are swapped every step (Alg. 2).  The grid carries, per
+ * voxel, the Arrhenius damage integral of Eq. (eq-tissState) and a latch of
+ * the 60 degC instantaneous-necrosis threshold (Introduction).  The RF source
+ * is a sum of Gaussian line sources, one per needle tine, each delivering a
+ * given power.
+ *
+ * The problem statement maps onto the calls: the label image with its class
+ * table is the initial condition g of Eq. (eq:setup) (Sec. "Implementation":
+ * labels replaced by tissue temperatures), the needle is the additional term
+ * f, held classes are the boundary condition h, and rfa_step advances N time
+ * steps (Alg. 1).
+ *
+ * The arterial blood temperature T_a of Eq. (2675-eq1_Kath) is 37 degC (the
+ * paper's value), which is also the initial temperature of free voxels.
+ *
+ * Conventions
+ *  - Layout: every voxel array is C order [nx][ny][nz], z fastest.
+ *  - Positions are metres in a frame centred on the grid: voxel i of n along
+ *    an axis of spacing d sits at (2 i - (n - 1)) d / 2.
+ *  - Units: SI (m, s, W, J, K); temperatures in degC.
+ *  - Ownership: inputs are copied during the call, the caller keeps its
+ *    buffers.  Outputs go to caller buffers.  A grid owns its device memory
+ *    until rfa_destroy_grid.
+ *  - Memory spaces: when rfa_options.inputs_on_device is set, every bulk voxel
+ *    array argument (labels, temperatures, masks, damage, perfusion fields) is
+ *    a device pointer on the grid's device; otherwise it is a host pointer.
+ *    Small arguments (class table, needle, diagnostics, dead volumes) are
+ *    always host memory.
+ *  - Streams: all device work of a grid is issued on rfa_options.stream (a
+ *    hipStream_t; NULL = the default stream).  Calls that write host outputs
+ *    synchronise that stream before returning.
+ *  - Errors: every call returns a status; nothing is thrown across the ABI.
+ *    On error the grid is left as it was before the call (set_* calls
+ *    validate everything before touching device state), and
+ *    rfa_last_error() describes the failure (thread-local).
+ *  - Threads: one grid per host thread at a time; distinct grids are
+ *    independent.
+ */
+#ifndef RFA_H_
+#define RFA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rfa_grid_s* rfa_grid; /* opaque handle, owned by the library */
+
+typedef enum {
+  RFA_OK = 0,
+  RFA_ERR_ARG = 1,      /* invalid argument (sizes, NaN, label out of range) */
+  RFA_ERR_STATE = 2,    /* call out of order (e.g. step before set_tissue)  */
+  RFA_ERR_UNSTABLE = 3, /* dt above the explicit scheme's stability bound   */
+  RFA_ERR_OOM = 4,      /* device allocation failed                         */
+  RFA_ERR_HIP = 5,      /* HIP runtime error                                */
+  RFA_ERR_NUMERIC = 6   /* NaN/Inf in the state after a step                */
+} rfa_status;
+
+/* One tissue class (Sec. "Specialized Methods for Liver Ablation
+ * Simulation": rho, c_p, K, w_b c_b, Q_m; Eq. (2675-eq6) / Alg. 1 for held
+ * classes). */
+typedef struct {
+  double k;        /* thermal conductivity K, W/m/K (>= 0)                    */
+  double rho;      /* density, kg/m^3 (> 0)                                   */
+  double c;        /* specific heat capacity c_p, J/kg/K (> 0)                */
+  double h_perf;   /* volumetric perfusion coefficient w_b c_b, W/m^3/K (>= 0)*/
+  double q_met;    /* metabolic heat Q_m, W/m^3                               */
+  double t_fixed;  /* temperature of a held class, degC (used iff fixed)      */
+  int fixed;       /* 1: voxels of this class keep their value                */
+  int tissue;      /* 1: voxels of this class accumulate damage               */
+} rfa_tissue;
+
+/* RF needle: tine t is the polyline pts[pt_offset[t] .. pt_offset[t+1]-1]
+ * (xyz triples, metres, grid-centre frame) delivering power[t] watts as a
+ * uniform line density convolved with an isotropic Gaussian of standard
+ * deviation sigma (metres).  Each tine's field is zeroed on held voxels and
+ * scaled so the tine delivers exactly power[t] on the grid. */
+typedef struct {
+  int n_tines;            /* 0 clears the source                           */
+  const int* pt_offset;   /* [n_tines + 1], increasing, >= 2 points a tine */
+  const double* pts;      /* [3 * pt_offset[n_tines]]                      */
+  const double* power;    /* [n_tines], W, >= 0                            */
+  double sigma;           /* m, > 0                                        */
+} rfa_needle;
+
+/* Grid options; rfa_default_options fills the defaults given per field. */
+typedef struct {
+  double t_death;     /* necrosis latch threshold, degC (60)                */
+  double A;           /* Arrhenius frequency factor, 1/s (7.39e39)          */
+  double Ea;          /* activation energy, J/mol (2.577e5)                 */
+  double R;           /* gas constant, J/mol/K (8.314)                      */
+  double omega_cap;   /* cap of the damage integral (1e30)                  */
+  void* stream;       /* hipStream_t for all device work (NULL)            */
+  int inputs_on_device; /* bulk voxel arrays are device pointers (0)        */
+  int depth;          /* steps per kernel launch; 0 = automatic (0)         */
+  int kernel;         /* 0 automatic, 1 reference one-thread-per-voxel,
+                         2 tiled 2.5-D (0)                                   */
+  int tile_y;         /* tiled kernel: y rows per work-group (4, 8, 16);
+                         0 = automatic (0)                                   */
+  int tile_x;         /* tiled kernel: x planes per work-group; 0 = auto (0)*/
+  int time_kernels;   /* N > 0: time step-kernel launches with HIP events,
+                         one event pair per block of N consecutive launches
+                         (read with rfa_kernel_stats); 0 = off (0)           */
+} rfa_options;
+
+/* Diagnostics of one rfa_step call (energies relative to 37 degC, J). */
+typedef struct {
+  double energy_J;        /* heat content of free voxels after the call      */
+  double injected_J;      /* RF + metabolic heat added during the call       */
+  double perfusion_J;     /* heat removed by perfusion during the call       */
+  double boundary_J;      /* heat received from held voxels during the call  */
+  double residual_J;      /* energy change - (injected - perfusion + boundary)*/
+  long long mono_violations; /* sum over steps of free voxels that cooled    */
+  double t_min_C, t_max_C;   /* temperature range after the call            */
+  long long steps;           /* steps taken by the call                      */
+} rfa_diag;
+
+rfa_status rfa_default_options(rfa_options* opt);
+
+/* Create an nx x ny x nz grid (each >= 3) with spacing dx, dy, dz metres.
+ * opt may be NULL (defaults).  The grid has no tissue until rfa_set_tissue. */
+rfa_status rfa_create_grid(int nx, int ny, int nz, double dx, double dy, double dz,
+                           const rfa_options* opt, rfa_grid* out);
+
+/* Set the class image and the class table (n_classes in 1..16) and reset the
+ * state: held classes at t_fixed, all other voxels at 37 degC, damage 0,
+ * latches from the initial temperatures.  The outermost voxel layer of the
+ * grid is always held at its initial value.  Labels >= n_classes give
+ * RFA_ERR_ARG.  (Sec. "Implementation": CT labels -> thermal start image.) */
+rfa_status rfa_set_tissue(rfa_grid g, const uint8_t* labels, const rfa_tissue* table,
+                          int n_classes);
+
+/* Rasterise the needle's RF power density on the grid (FP64 on the device).
+ * Requires tissue (held voxels receive no power).  n_tines == 0 clears it.
+ * A tine with no weight on free voxels gives RFA_ERR_ARG. */
+rfa_status rfa_set_needle(rfa_grid g, const rfa_needle* needle);
+
+/* Per-voxel multiplier of the class perfusion coefficient (h = h_class * f),
+ * f >= 0, [nx*ny*nz] float; NULL removes it (f = 1). */
+rfa_status rfa_set_perfusion(rfa_grid g, const float* factor);
+
+/* Advance n_steps explicit steps of length dt seconds (Eq. (CUDAbioheat3d),
+ * Alg. 1 and 2).  dt above the bound min over free voxels of
+ * rho c / (sum_faces K_face / d^2 + h) gives RFA_ERR_UNSTABLE.  diag may be
+ * NULL; if given, the call also sums per-step diagnostics and synchronises. */
+rfa_status rfa_step(rfa_grid g, int n_steps, double dt, rfa_diag* diag);
+
+/* Largest dt accepted by rfa_step for the current tissue and perfusion. */
+rfa_status rfa_dt_max(rfa_grid g, double* dt_max);
+
+/* Damage outputs (any may be NULL): mask bit0 = latched T >= t_death,
+ * bit1 = damage integral >= 1 (tissue classes only); omega = damage
+ * integral (float); dead_m3[2*n_classes] = per class dead volume by bit0
+ * then by bit1, m^3. */
+rfa_status rfa_damage(rfa_grid g, uint8_t* mask, float* omega, double* dead_m3);
+
+/* Temperature outputs (any may be NULL): t_C = 37 + hi + lo summed in FP64,
+ * degC; hi, lo = the raw float-float excess-temperature state. */
+rfa_status rfa_get_temperature(rfa_grid g, double* t_C, float* hi, float* lo);
+
+/* Overwrite the temperature state (degC, double, [nx*ny*nz]); damage and
+ * latches are kept.  Held voxels take the given values as well. */
+rfa_status rfa_set_temperature(rfa_grid g, const double* t_C);
+
+/* Serialise / restore the full dynamic state (temperature, damage, latches,
+ * step count) with a checksum.  bytes: in = capacity, out = size needed
+ * (call with buf == NULL to query).  A buffer from another grid shape or a
+ * corrupted one gives RFA_ERR_STATE. */
+rfa_status rfa_save_state(rfa_grid g, void* buf, size_t* bytes);
+rfa_status rfa_load_state(rfa_grid g, const void* buf, size_t bytes);
+
+/* Steps taken since the last rfa_set_tissue / rfa_load_state. */
+rfa_status rfa_get_step_count(rfa_grid g, long long* steps);
+
+/* Step-kernel timing accumulated since the last call (requires
+ * rfa_options.time_kernels): total milliseconds measured with HIP events
+ * around blocks of consecutive step-kernel launches (diagnostic reductions
+ * excluded), number of launches in those blocks, voxel-steps they advanced.
+ * Resets the counters.  Any argument may be NULL. */
+rfa_status rfa_kernel_stats(rfa_grid g, double* kernel_ms, long long* launches,
+                            long long* voxel_steps);
+
+/* Current launch plan: kernel (1 reference, 2 tiled), steps per launch,
+ * tile rows, x planes per work-group, work-groups per launch. */
+rfa_status rfa_get_plan(rfa_grid g, int* kernel, int* depth, int* tile_y, int* tile_x,
+                        int* workgroups);
+
+/* Time the candidate launch plans of this grid's shape on scratch copies of
+ * its state (the state is not advanced) and keep the fastest.  dt as for
+ * rfa_step; reps launches per candidate.  Results are cached per grid shape
+ * for the process. */
+rfa_status rfa_tune(rfa_grid g, double dt, int reps);
+
+/* Measured device-to-device streaming-copy bandwidth over `bytes` bytes
+ * (read + write counted), GB/s: the achievable HBM ceiling on this device. */
+rfa_status rfa_copy_bandwidth(size_t bytes, int reps, double* gbps);
+
+void rfa_destroy_grid(rfa_grid g);
+const char* rfa_status_string(rfa_status s);
+const char* rfa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RFA_H_ */

@@ -1,0 +1,999 @@
+// rfa_api.hip -- runtime and C ABI of librfa.so (see include/rfa.h).
+//
+// The runtime owns the device state of a grid (ping-pong float-float
+// temperature images, label bytes with flags, damage integral, RF source,
+// coefficient tables), validates every argument before touching it,
+// rebuilds the per-dt coefficient tables and the source increment when dt
+// changes, and issues every kernel on the grid's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rfa.h"
+#include "rfa_kernels.h"
+#include "rfa_step.h"
+
+using namespace rfa;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rfa_status fail(rfa_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(RFA_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+constexpr int kPartialSlots = 64;  // steps of diagnostic partials per reduction
+constexpr int kTimedBatch = 1024;  // launches between event read-backs
+constexpr double kTBodyK = 310.15;
+constexpr double kExponentClamp = 80.0;
+
+}  // namespace
+
+struct rfa_grid_s {
+  Grid3 g{0, 0, 0};
+  double dx = 0, dy = 0, dz = 0;
+  rfa_options opt{};
+  hipStream_t st = nullptr;
+  int device = 0;
+
+  bool has_tissue = false;
+  int n_classes = 0;
+  rfa_tissue table[kMaxClasses]{};
+  ClassParams cp{};
+  ClassParams* cp_dev = nullptr;
+  unsigned long long free_count[kMaxClasses]{};
+
+  uint8_t* lab = nullptr;
+  float* hi[2] = {nullptr, nullptr};
+  float* lo[2] = {nullptr, nullptr};
+  int cur = 0;
+  float* om = nullptr;
+  float* src = nullptr;
+  double* q64 = nullptr;
+  float* perf = nullptr;  // null = no perfusion multiplier
+  Tables* tab_dev = nullptr;
+  Tables tab_host{};
+  double tab_dt = -1.0;
+  double src_dt = -1.0;
+
+  bool has_needle = false;
+  std::vector<int> pt_offset;
+  std::vector<double> pts, power;
+  double sigma = 0.0;
+  double rf_power = 0.0;
+
+  double dt_max = 0.0;
+  long long steps = 0;
+
+  // scratch
+  float* partials = nullptr;
+  size_t partial_floats = 0;
+  double* dacc = nullptr;          // [3] step partial accumulators
+  double* red = nullptr;           // reduction partials
+  size_t red_doubles = 0;
+  double* out4 = nullptr;          // [4] state reduction result
+  unsigned long long* counts = nullptr;  // [32]
+  unsigned* bad = nullptr;
+  double energy = 0.0;
+  bool energy_valid = false;
+
+  StepPlan plan{};
+  bool plan_tuned = false;
+
+  // step-kernel timing
+  std::vector<hipEvent_t> events;
+  double kernel_ms = 0.0;
+  long long kernel_launches = 0;
+  long long kernel_voxel_steps = 0;
+};
+
+namespace {
+
+void free_all(rfa_grid g) {
+  auto f = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  f(g->cp_dev);
+  f(g->lab);
+  f(g->hi[0]);
+  f(g->hi[1]);
+  f(g->lo[0]);
+  f(g->lo[1]);
+  f(g->om);
+  f(g->src);
+  f(g->q64);
+  f(g->perf);
+  f(g->tab_dev);
+  f(g->partials);
+  f(g->dacc);
+  f(g->red);
+  f(g->out4);
+  f(g->counts);
+  f(g->bad);
+  for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
+  g->events.clear();
+}
+
+template <class T>
+rfa_status dmalloc(T** p, size_t count) {
+  *p = nullptr;
+  hipError_t e = hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(RFA_ERR_OOM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                hipGetErrorString(e));
+  }
+  return RFA_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+hipMemcpyKind kind_in(const rfa_grid g) {
+  return g->opt.inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+}
+hipMemcpyKind kind_out(const rfa_grid g) {
+  return g->opt.inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+}
+
+// Harmonic-mean face conductivity (series resistance of two half voxels).
+double face_k(double a, double b) { return (a + b) == 0.0 ? 0.0 : 2.0 * a * b / (a + b); }
+
+void split(double v, float& hi, float& lo) {
+  hi = (float)v;
+  lo = (float)(v - (double)hi);
+}
+
+// Per-dt coefficient tables (FP64 -> float-float).
+void build_tables(rfa_grid g, double dt) {
+  Tables& T = g->tab_host;
+  std::memset(&T, 0, sizeof T);
+  const double d2[3] = {g->dx * g->dx, g->dy * g->dy, g->dz * g->dz};
+  const double vol = g->dx * g->dy * g->dz;
+  for (int a = 0; a < g->n_classes; ++a) {
+    const rfa_tissue& ta = g->table[a];
+    const double rc = ta.rho * ta.c;
+    for (int b = 0; b < g->n_classes; ++b) {
+      const double kf = face_k(ta.k, g->table[b].k);
+      for (int ax = 0; ax < 3; ++ax) {
+        float h, l;
+        split(dt * kf / (rc * d2[ax]), h, l);
+        T.cf[ax][a * kMaxClasses + b] = make_float2(h, l);
+      }
+    }
+    float bh, bl;
+    split(dt * ta.h_perf / rc, bh, bl);
+    T.cls[a] = make_float4(bh, bl, (float)(dt * ta.q_met / rc), (float)(rc * vol));
+  }
+}
+
+StepConst step_const(rfa_grid g, double dt) {
+  StepConst K;
+  const double c = g->opt.Ea / (g->opt.R * kTBodyK);
+  K.dtka = (float)(dt * g->opt.A * std::exp(-c));
+  K.c2 = (float)(c * M_LOG2E);
+  K.tak = (float)kTBodyK;
+  K.clamp2 = (float)(kExponentClamp * M_LOG2E);
+  K.cap = (float)g->opt.omega_cap;
+  K.thr = (float)(g->opt.t_death - 37.0);
+  return K;
+}
+
+rfa_status compute_dt_max(rfa_grid g) {
+  int nblk = 0;
+  HIP_TRY(launch_dt_bound(g->g, g->lab, g->perf, g->cp_dev, 1.0 / (g->dx * g->dx),
+                          1.0 / (g->dy * g->dy), 1.0 / (g->dz * g->dz), g->red, &nblk,
+                          g->out4, g->st));
+  double v = 0.0;
+  HIP_TRY(hipMemcpyAsync(&v, g->out4, sizeof v, hipMemcpyDeviceToHost, g->st));
+  HIP_TRY(hipStreamSynchronize(g->st));
+  g->dt_max = v;
+  return RFA_OK;
+}
+
+// Rasterise the stored needle into q64 (zero if none) and invalidate s.
+rfa_status rasterise(rfa_grid g) {
+  g->src_dt = -1.0;
+  if (!g->has_needle) {
+    HIP_TRY(hipMemsetAsync(g->q64, 0, g->g.n() * sizeof(double), g->st));
+    g->rf_power = 0.0;
+    return RFA_OK;
+  }
+  const int nt = (int)g->power.size();
+  std::vector<Chord> chords;
+  std::vector<int> first(nt + 1, 0);
+  for (int t = 0; t < nt; ++t) {
+    first[t] = (int)chords.size();
+    for (int p = g->pt_offset[t]; p + 1 < g->pt_offset[t + 1]; ++p) {
+      const double* a = &g->pts[3 * p];
+      const double* b = &g->pts[3 * (p + 1)];
+      const double ux = b[0] - a[0], uy = b[1] - a[1], uz = b[2] - a[2];
+      const double len = std::sqrt(ux * ux + uy * uy + uz * uz);
+      if (len == 0.0) continue;
+      Chord c;
+      c.mx = 0.5 * (a[0] + b[0]);
+      c.my = 0.5 * (a[1] + b[1]);
+      c.mz = 0.5 * (a[2] + b[2]);
+      c.ux = ux / len;
+      c.uy = uy / len;
+      c.uz = uz / len;
+      c.half = 0.5 * len;
+      c.tine = t;
+      c.pad = 0;
+      chords.push_back(c);
+    }
+  }
+  first[nt] = (int)chords.size();
+  Chord* d_chords = nullptr;
+  int* d_first = nullptr;
+  double* d_sums = nullptr;
+  double* d_partial = nullptr;
+  rfa_status s;
+  if ((s = dmalloc(&d_chords, chords.size())) != RFA_OK) return s;
+  if ((s = dmalloc(&d_first, first.size())) != RFA_OK) { (void)hipFree(d_chords); return s; }
+  if ((s = dmalloc(&d_sums, 2 * (size_t)nt)) != RFA_OK) {
+    (void)hipFree(d_chords); (void)hipFree(d_first); return s;
+  }
+  if ((s = dmalloc(&d_partial, (size_t)nt * 1024)) != RFA_OK) {
+    (void)hipFree(d_chords); (void)hipFree(d_first); (void)hipFree(d_sums); return s;
+  }
+  auto cleanup = [&]() {
+    (void)hipFree(d_chords);
+    (void)hipFree(d_first);
+    (void)hipFree(d_sums);
+    (void)hipFree(d_partial);
+  };
+  std::vector<double> sums(nt), scale(nt);
+  hipError_t e = hipSuccess;
+  int nblk = 0;
+  do {
+    if ((e = hipMemcpyAsync(d_chords, chords.data(), chords.size() * sizeof(Chord),
+                            hipMemcpyHostToDevice, g->st)) != hipSuccess) break;
+    if ((e = hipMemcpyAsync(d_first, first.data(), first.size() * sizeof(int),
+                            hipMemcpyHostToDevice, g->st)) != hipSuccess) break;
+    if ((e = launch_source_sums(g->g, g->dx, g->dy, g->dz, g->lab, d_chords, d_first, nt,
+                                g->sigma, d_partial, &nblk, d_sums, g->st)) != hipSuccess) break;
+    if ((e = hipMemcpyAsync(sums.data(), d_sums, nt * sizeof(double), hipMemcpyDeviceToHost,
+                            g->st)) != hipSuccess) break;
+    if ((e = hipStreamSynchronize(g->st)) != hipSuccess) break;
+  } while (false);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(RFA_ERR_HIP, "source rasterisation failed: %s", hipGetErrorString(e));
+  }
+  for (int t = 0; t < nt; ++t) {
+    if (!(sums[t] > 0.0)) {
+      cleanup();
+      return fail(RFA_ERR_ARG, "tine %d has no weight on free voxels", t);
+    }
+    scale[t] = g->power[t] / sums[t];
+  }
+  do {
+    if ((e = hipMemcpyAsync(d_sums + nt, scale.data(), nt * sizeof(double),
+                            hipMemcpyHostToDevice, g->st)) != hipSuccess) break;
+    if ((e = launch_source_write(g->g, g->dx, g->dy, g->dz, g->lab, d_chords, d_first, nt,
+                                 g->sigma, d_sums + nt, g->q64, g->st)) != hipSuccess) break;
+    if ((e = hipStreamSynchronize(g->st)) != hipSuccess) break;
+  } while (false);
+  cleanup();
+  if (e != hipSuccess) return fail(RFA_ERR_HIP, "source write failed: %s", hipGetErrorString(e));
+  double tot = 0.0;
+  for (double p : g->power) tot += p;
+  g->rf_power = tot;
+  return RFA_OK;
+}
+
+rfa_status ensure_events(rfa_grid g, int count) {
+  while ((int)g->events.size() < count) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    g->events.push_back(e);
+  }
+  return RFA_OK;
+}
+
+rfa_status state_reduce(rfa_grid g, double out[4]) {
+  HIP_TRY(launch_state_reduce(g->g, g->lab, g->hi[g->cur], g->lo[g->cur], g->cp_dev,
+                              g->dx * g->dy * g->dz, g->red, g->out4, g->st));
+  HIP_TRY(hipMemcpyAsync(out, g->out4, 4 * sizeof(double), hipMemcpyDeviceToHost, g->st));
+  HIP_TRY(hipStreamSynchronize(g->st));
+  return RFA_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+rfa_status rfa_default_options(rfa_options* opt) {
+  if (!opt) return fail(RFA_ERR_ARG, "opt is NULL");
+  std::memset(opt, 0, sizeof *opt);
+  opt->t_death = 60.0;
+  opt->A = 7.39e39;
+  opt->Ea = 2.577e5;
+  opt->R = 8.314;
+  opt->omega_cap = 1e30;
+  opt->stream = nullptr;
+  opt->inputs_on_device = 0;
+  opt->depth = 0;
+  opt->kernel = 0;
+  opt->tile_y = 0;
+  opt->tile_x = 0;
+  opt->time_kernels = 0;
+  return RFA_OK;
+}
+
+rfa_status rfa_create_grid(int nx, int ny, int nz, double dx, double dy, double dz,
+                           const rfa_options* opt, rfa_grid* out) {
+  if (!out) return fail(RFA_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (nx < 3 || ny < 3 || nz < 3) return fail(RFA_ERR_ARG, "grid must be at least 3^3");
+  if ((double)nx * ny * nz > 4.0e9) return fail(RFA_ERR_ARG, "grid too large");
+  if (!finite_pos(dx) || !finite_pos(dy) || !finite_pos(dz))
+    return fail(RFA_ERR_ARG, "spacing must be finite and positive");
+  rfa_options o;
+  if (opt) {
+    o = *opt;
+  } else {
+    rfa_default_options(&o);
+  }
+  if (!std::isfinite(o.t_death) || !(o.A >= 0.0) || !std::isfinite(o.A) || !finite_pos(o.Ea) ||
+      !finite_pos(o.R) || !finite_pos(o.omega_cap) || o.omega_cap > 3.0e38)
+    return fail(RFA_ERR_ARG, "invalid damage options");
+  if (o.depth < 0 || o.depth > kMaxDepth) return fail(RFA_ERR_ARG, "depth out of range");
+  if (o.kernel < 0 || o.kernel > 2) return fail(RFA_ERR_ARG, "kernel must be 0, 1 or 2");
+  if (o.tile_y != 0 && o.tile_y != 4 && o.tile_y != 8 && o.tile_y != 16)
+    return fail(RFA_ERR_ARG, "tile_y must be 0, 4, 8 or 16");
+  if (o.tile_x < 0) return fail(RFA_ERR_ARG, "tile_x must be >= 0");
+  if (o.time_kernels < 0 || o.time_kernels > kTimedBatch)
+    return fail(RFA_ERR_ARG, "time_kernels must be in 0..%d", kTimedBatch);
+  rfa_grid g = new (std::nothrow) rfa_grid_s();
+  if (!g) return fail(RFA_ERR_OOM, "host allocation failed");
+  g->g = Grid3{nx, ny, nz};
+  g->dx = dx;
+  g->dy = dy;
+  g->dz = dz;
+  g->opt = o;
+  g->st = (hipStream_t)o.stream;
+  if (hipGetDevice(&g->device) != hipSuccess) {
+    delete g;
+    return fail(RFA_ERR_HIP, "no HIP device");
+  }
+  const size_t n = g->g.n();
+  g->plan = plan_default(g->g, o.kernel, o.tile_y, o.tile_x);
+  const size_t nwg = (size_t)plan_max_wg(g->g);
+  g->partial_floats = nwg * 3 * kPartialSlots;
+  g->red_doubles = 4 * 1024 + 64;
+  rfa_status s = RFA_OK;
+  if ((s = dmalloc(&g->cp_dev, 1)) || (s = dmalloc(&g->lab, n)) || (s = dmalloc(&g->hi[0], n)) ||
+      (s = dmalloc(&g->hi[1], n)) || (s = dmalloc(&g->lo[0], n)) || (s = dmalloc(&g->lo[1], n)) ||
+      (s = dmalloc(&g->om, n)) || (s = dmalloc(&g->src, n)) || (s = dmalloc(&g->q64, n)) ||
+      (s = dmalloc(&g->tab_dev, 1)) || (s = dmalloc(&g->partials, g->partial_floats)) ||
+      (s = dmalloc(&g->dacc, 4)) || (s = dmalloc(&g->red, g->red_doubles)) ||
+      (s = dmalloc(&g->out4, 4)) || (s = dmalloc(&g->counts, 2 * kMaxClasses)) ||
+      (s = dmalloc(&g->bad, 1))) {
+    free_all(g);
+    delete g;
+    return s;
+  }
+  *out = g;
+  return RFA_OK;
+}
+
+rfa_status rfa_set_tissue(rfa_grid g, const uint8_t* labels, const rfa_tissue* table,
+                          int n_classes) {
+  if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
+  if (!labels || !table) return fail(RFA_ERR_ARG, "labels and table are required");
+  if (n_classes < 1 || n_classes > kMaxClasses)
+    return fail(RFA_ERR_ARG, "n_classes must be in 1..%d", kMaxClasses);
+  for (int c = 0; c < n_classes; ++c) {
+    const rfa_tissue& t = table[c];
+    if (!(t.k >= 0.0) || !std::isfinite(t.k) || !finite_pos(t.rho) || !finite_pos(t.c) ||
+        !(t.h_perf >= 0.0) || !std::isfinite(t.h_perf) || !std::isfinite(t.q_met) ||
+        (t.fixed && !std::isfinite(t.t_fixed)) || (t.fixed != 0 && t.fixed != 1) ||
+        (t.tissue != 0 && t.tissue != 1))
+      return fail(RFA_ERR_ARG, "invalid parameters in class %d", c);
+  }
+  const size_t n = g->g.n();
+  if (!g->opt.inputs_on_device) {
+    for (size_t p = 0; p < n; ++p)
+      if (labels[p] >= n_classes)
+        return fail(RFA_ERR_ARG, "label %d at voxel %zu >= n_classes", labels[p], p);
+  }
+  ClassParams cp{};
+  for (int c = 0; c < n_classes; ++c) {
+    cp.k[c] = table[c].k;
+    cp.rc[c] = table[c].rho * table[c].c;
+    cp.h[c] = table[c].h_perf;
+    cp.t_fixed[c] = table[c].t_fixed;
+    cp.fixed[c] = table[c].fixed;
+    cp.tissue[c] = table[c].tissue;
+  }
+  cp.n = n_classes;
+  // Build the new label bytes into a fresh buffer so an invalid device label
+  // image leaves the grid untouched.
+  uint8_t* user = nullptr;
+  uint8_t* nlab = nullptr;
+  ClassParams* ncp = nullptr;
+  rfa_status s;
+  if ((s = dmalloc(&nlab, n)) != RFA_OK) return s;
+  if ((s = dmalloc(&ncp, 1)) != RFA_OK) { (void)hipFree(nlab); return s; }
+  if (!g->opt.inputs_on_device) {
+    if ((s = dmalloc(&user, n)) != RFA_OK) { (void)hipFree(nlab); (void)hipFree(ncp); return s; }
+  }
+  unsigned bad = 0;
+  hipError_t e = hipSuccess;
+  do {
+    if (user && (e = hipMemcpyAsync(user, labels, n, hipMemcpyHostToDevice, g->st)) != hipSuccess)
+      break;
+    if ((e = hipMemcpyAsync(ncp, &cp, sizeof cp, hipMemcpyHostToDevice, g->st)) != hipSuccess) break;
+    if ((e = hipMemsetAsync(g->bad, 0, sizeof(unsigned), g->st)) != hipSuccess) break;
+    if ((e = launch_build_labels(g->g, user ? user : labels, nlab, ncp, g->bad, g->st)) !=
+        hipSuccess) break;
+    if ((e = hipMemcpyAsync(&bad, g->bad, sizeof bad, hipMemcpyDeviceToHost, g->st)) != hipSuccess)
+      break;
+    if ((e = hipStreamSynchronize(g->st)) != hipSuccess) break;
+  } while (false);
+  if (user) (void)hipFree(user);
+  if (e != hipSuccess || bad) {
+    (void)hipFree(nlab);
+    (void)hipFree(ncp);
+    if (e != hipSuccess) return fail(RFA_ERR_HIP, "set_tissue failed: %s", hipGetErrorString(e));
+    return fail(RFA_ERR_ARG, "%u labels >= n_classes", bad);
+  }
+  // commit
+  (void)hipFree(g->lab);
+  (void)hipFree(g->cp_dev);
+  g->lab = nlab;
+  g->cp_dev = ncp;
+  g->cp = cp;
+  g->n_classes = n_classes;
+  std::memcpy(g->table, table, n_classes * sizeof(rfa_tissue));
+  g->has_tissue = true;
+  g->cur = 0;
+  g->steps = 0;
+  g->tab_dt = -1.0;
+  g->src_dt = -1.0;
+  g->energy_valid = false;
+  HIP_TRY(launch_reset_state(g->g, g->lab, g->hi[0], g->lo[0], g->om, g->cp_dev,
+                             (float)(g->opt.t_death - 37.0), g->st));
+  HIP_TRY(hipMemsetAsync(g->counts, 0, 2 * kMaxClasses * sizeof(unsigned long long), g->st));
+  HIP_TRY(launch_free_counts(g->g, g->lab, g->counts, g->st));
+  HIP_TRY(hipMemcpyAsync(g->free_count, g->counts, kMaxClasses * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, g->st));
+  HIP_TRY(hipStreamSynchronize(g->st));
+  if ((s = compute_dt_max(g)) != RFA_OK) return s;
+  return rasterise(g);
+}
+
+rfa_status rfa_set_needle(rfa_grid g, const rfa_needle* nd) {
+  if (!g || !nd) return fail(RFA_ERR_ARG, "grid and needle are required");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "set_tissue before set_needle");
+  if (nd->n_tines < 0 || nd->n_tines > 4096) return fail(RFA_ERR_ARG, "n_tines out of range");
+  if (nd->n_tines == 0) {
+    g->has_needle = false;
+    g->pt_offset.clear();
+    g->pts.clear();
+    g->power.clear();
+    return rasterise(g);
+  }
+  if (!nd->pt_offset || !nd->pts || !nd->power) return fail(RFA_ERR_ARG, "needle arrays missing");
+  if (!finite_pos(nd->sigma)) return fail(RFA_ERR_ARG, "sigma must be positive");
+  if (nd->pt_offset[0] != 0) return fail(RFA_ERR_ARG, "pt_offset[0] must be 0");
+  for (int t = 0; t < nd->n_tines; ++t) {
+    if (nd->pt_offset[t + 1] - nd->pt_offset[t] < 2)
+      return fail(RFA_ERR_ARG, "tine %d has fewer than 2 points", t);
+    if (!(nd->power[t] >= 0.0) || !std::isfinite(nd->power[t]))
+      return fail(RFA_ERR_ARG, "power of tine %d must be finite and >= 0", t);
+  }
+  const int np = nd->pt_offset[nd->n_tines];
+  for (int i = 0; i < 3 * np; ++i)
+    if (!std::isfinite(nd->pts[i])) return fail(RFA_ERR_ARG, "needle point not finite");
+  // keep the previous needle to restore on failure
+  auto old_off = g->pt_offset;
+  auto old_pts = g->pts;
+  auto old_pw = g->power;
+  double old_sigma = g->sigma;
+  bool old_has = g->has_needle;
+  g->pt_offset.assign(nd->pt_offset, nd->pt_offset + nd->n_tines + 1);
+  g->pts.assign(nd->pts, nd->pts + 3 * np);
+  g->power.assign(nd->power, nd->power + nd->n_tines);
+  g->sigma = nd->sigma;
+  g->has_needle = true;
+  rfa_status s = rasterise(g);
+  if (s != RFA_OK) {
+    std::string err = g_last_error;
+    g->pt_offset = old_off;
+    g->pts = old_pts;
+    g->power = old_pw;
+    g->sigma = old_sigma;
+    g->has_needle = old_has;
+    rasterise(g);
+    g_last_error = err;
+  }
+  return s;
+}
+
+rfa_status rfa_set_perfusion(rfa_grid g, const float* factor) {
+  if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "set_tissue before set_perfusion");
+  const size_t n = g->g.n();
+  if (!factor) {
+    if (g->perf) (void)hipFree(g->perf);
+    g->perf = nullptr;
+    return compute_dt_max(g);
+  }
+  if (!g->opt.inputs_on_device) {
+    for (size_t p = 0; p < n; ++p)
+      if (!(factor[p] >= 0.0f) || !std::isfinite(factor[p]))
+        return fail(RFA_ERR_ARG, "perfusion factor at voxel %zu is not finite and >= 0", p);
+  }
+  if (!g->perf) {
+    rfa_status s = dmalloc(&g->perf, n);
+    if (s != RFA_OK) return s;
+  }
+  HIP_TRY(hipMemcpyAsync(g->perf, factor, n * sizeof(float), kind_in(g), g->st));
+  return compute_dt_max(g);
+}
+
+rfa_status rfa_dt_max(rfa_grid g, double* dt_max) {
+  if (!g || !dt_max) return fail(RFA_ERR_ARG, "grid and dt_max are required");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "no tissue");
+  *dt_max = g->dt_max;
+  return RFA_OK;
+}
+
+rfa_status rfa_step(rfa_grid g, int n_steps, double dt, rfa_diag* diag) {
+  if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "set_tissue before step");
+  if (n_steps < 0) return fail(RFA_ERR_ARG, "n_steps must be >= 0");
+  if (!finite_pos(dt)) return fail(RFA_ERR_ARG, "dt must be finite and positive");
+  if (dt > g->dt_max)
+    return fail(RFA_ERR_UNSTABLE, "dt %.6g s exceeds the stability bound %.6g s", dt, g->dt_max);
+  if (dt != g->tab_dt) {
+    build_tables(g, dt);
+    HIP_TRY(hipMemcpyAsync(g->tab_dev, &g->tab_host, sizeof(Tables), hipMemcpyHostToDevice, g->st));
+    HIP_TRY(hipStreamSynchronize(g->st));
+    g->tab_dt = dt;
+  }
+  if (dt != g->src_dt) {
+    HIP_TRY(launch_source_increment(g->g, g->lab, g->q64, g->cp_dev, dt, g->src, g->st));
+    g->src_dt = dt;
+  }
+  const StepConst K = step_const(g, dt);
+  double e0 = 0.0;
+  if (diag) {
+    if (!g->energy_valid) {
+      double r[4];
+      rfa_status s = state_reduce(g, r);
+      if (s != RFA_OK) return s;
+      g->energy = r[0];
+      g->energy_valid = true;
+    }
+    e0 = g->energy;
+    HIP_TRY(hipMemsetAsync(g->dacc, 0, 4 * sizeof(double), g->st));
+  }
+  StepState ss{g->hi, g->lo, &g->cur, g->lab, g->src, g->om, g->perf, g->tab_dev,
+               g->n_classes};
+  rfa_status s = RFA_OK;
+  for (int done = 0; done < n_steps;) {
+    const int batch = std::min(n_steps - done, kTimedBatch);
+    hipEvent_t* ev = nullptr;
+    if (g->opt.time_kernels) {
+      if ((s = ensure_events(g, 2 * batch)) != RFA_OK) return s;
+      ev = g->events.data();
+    }
+    int timed = 0;
+    s = run_steps(g->g, g->plan, ss, K, batch, diag ? g->partials : nullptr, kPartialSlots,
+                  g->dacc, ev, g->opt.time_kernels, &timed, g->st);
+    if (s != RFA_OK)
+      return fail(s, "step launch failed: %s", hipGetErrorString(hipGetLastError()));
+    if (ev && timed > 0) {
+      HIP_TRY(hipEventSynchronize(ev[2 * timed - 1]));
+      for (int k = 0; k < timed; ++k) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+        g->kernel_ms += ms;
+      }
+      g->kernel_launches += batch;
+      g->kernel_voxel_steps += (long long)batch * g->plan.depth * (long long)g->g.n();
+    }
+    done += batch;
+    g->steps += batch;
+  }
+  if (n_steps > 0) g->energy_valid = false;
+  if (diag) {
+    double acc[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(acc, g->dacc, 3 * sizeof(double), hipMemcpyDeviceToHost, g->st));
+    double r[4];
+    s = state_reduce(g, r);
+    if (s != RFA_OK) return s;
+    g->energy = r[0];
+    g->energy_valid = true;
+    const double vol = g->dx * g->dy * g->dz;
+    double met = 0.0;
+    for (int c = 0; c < g->n_classes; ++c)
+      met += g->table[c].q_met * (double)g->free_count[c] * vol;
+    diag->energy_J = r[0];
+    diag->injected_J = (g->rf_power + met) * dt * n_steps;
+    diag->perfusion_J = acc[0];
+    diag->boundary_J = acc[1];
+    diag->residual_J = (r[0] - e0) - (diag->injected_J - diag->perfusion_J + diag->boundary_J);
+    diag->mono_violations = (long long)std::llround(acc[2]);
+    diag->t_min_C = r[1];
+    diag->t_max_C = r[2];
+    diag->steps = n_steps;
+    if (r[3] > 0.0) return fail(RFA_ERR_NUMERIC, "%.0f non-finite voxels after step", r[3]);
+  }
+  return RFA_OK;
+}
+
+rfa_status rfa_damage(rfa_grid g, uint8_t* mask, float* omega, double* dead_m3) {
+  if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "no tissue");
+  const size_t n = g->g.n();
+  uint8_t* dmask = nullptr;
+  if (mask) {
+    if (g->opt.inputs_on_device) {
+      dmask = mask;
+    } else {
+      rfa_status s = dmalloc(&dmask, n);
+      if (s != RFA_OK) return s;
+    }
+  }
+  hipError_t e = hipSuccess;
+  unsigned long long cnt[2 * kMaxClasses] = {};
+  do {
+    if ((e = hipMemsetAsync(g->counts, 0, sizeof cnt, g->st)) != hipSuccess) break;
+    if ((e = launch_damage(g->g, g->lab, g->om, dmask, g->counts, g->st)) != hipSuccess) break;
+    if (mask && !g->opt.inputs_on_device &&
+        (e = hipMemcpyAsync(mask, dmask, n, hipMemcpyDeviceToHost, g->st)) != hipSuccess) break;
+    if (omega && (e = hipMemcpyAsync(omega, g->om, n * sizeof(float), kind_out(g), g->st)) !=
+                     hipSuccess) break;
+    if ((e = hipMemcpyAsync(cnt, g->counts, sizeof cnt, hipMemcpyDeviceToHost, g->st)) !=
+        hipSuccess) break;
+    if ((e = hipStreamSynchronize(g->st)) != hipSuccess) break;
+  } while (false);
+  if (dmask && dmask != mask) (void)hipFree(dmask);
+  if (e != hipSuccess) return fail(RFA_ERR_HIP, "damage failed: %s", hipGetErrorString(e));
+  if (dead_m3) {
+    const double vol = g->dx * g->dy * g->dz;
+    for (int c = 0; c < g->n_classes; ++c) {
+      dead_m3[2 * c] = (double)cnt[2 * c] * vol;
+      dead_m3[2 * c + 1] = (double)cnt[2 * c + 1] * vol;
+    }
+  }
+  return RFA_OK;
+}
+
+rfa_status rfa_get_temperature(rfa_grid g, double* t_C, float* hi, float* lo) {
+  if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "no tissue");
+  const size_t n = g->g.n();
+  if (t_C) {
+    double* dt = nullptr;
+    if (g->opt.inputs_on_device) {
+      dt = t_C;
+    } else {
+      rfa_status s = dmalloc(&dt, n);
+      if (s != RFA_OK) return s;
+    }
+    hipError_t e = launch_temperature_out(g->g, g->hi[g->cur], g->lo[g->cur], dt, g->st);
+    if (e == hipSuccess && dt != t_C)
+      e = hipMemcpyAsync(t_C, dt, n * sizeof(double), hipMemcpyDeviceToHost, g->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+    if (dt != t_C) (void)hipFree(dt);
+    if (e != hipSuccess) return fail(RFA_ERR_HIP, "get_temperature: %s", hipGetErrorString(e));
+  }
+  if (hi) HIP_TRY(hipMemcpyAsync(hi, g->hi[g->cur], n * sizeof(float), kind_out(g), g->st));
+  if (lo) HIP_TRY(hipMemcpyAsync(lo, g->lo[g->cur], n * sizeof(float), kind_out(g), g->st));
+  HIP_TRY(hipStreamSynchronize(g->st));
+  return RFA_OK;
+}
+
+rfa_status rfa_set_temperature(rfa_grid g, const double* t_C) {
+  if (!g || !t_C) return fail(RFA_ERR_ARG, "grid and t_C are required");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "no tissue");
+  const size_t n = g->g.n();
+  if (!g->opt.inputs_on_device) {
+    for (size_t p = 0; p < n; ++p)
+      if (!std::isfinite(t_C[p])) return fail(RFA_ERR_ARG, "temperature not finite at %zu", p);
+  }
+  const double* src = t_C;
+  double* tmp = nullptr;
+  if (!g->opt.inputs_on_device) {
+    rfa_status s = dmalloc(&tmp, n);
+    if (s != RFA_OK) return s;
+    hipError_t e = hipMemcpyAsync(tmp, t_C, n * sizeof(double), hipMemcpyHostToDevice, g->st);
+    if (e != hipSuccess) {
+      (void)hipFree(tmp);
+      return fail(RFA_ERR_HIP, "set_temperature: %s", hipGetErrorString(e));
+    }
+    src = tmp;
+  }
+  hipError_t e = launch_temperature_in(g->g, src, g->hi[g->cur], g->lo[g->cur], g->lab,
+                                       (float)(g->opt.t_death - 37.0), g->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(RFA_ERR_HIP, "set_temperature: %s", hipGetErrorString(e));
+  g->energy_valid = false;
+  return RFA_OK;
+}
+
+// ---- checkpoint ---------------------------------------------------------------
+namespace {
+struct StateHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t nx, ny, nz;
+  int64_t steps;
+  uint64_t payload;
+  uint64_t checksum;
+};
+
+uint64_t fnv1a(const uint8_t* p, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+}  // namespace
+
+rfa_status rfa_save_state(rfa_grid g, void* buf, size_t* bytes) {
+  if (!g || !bytes) return fail(RFA_ERR_ARG, "grid and bytes are required");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "no tissue");
+  const size_t n = g->g.n();
+  const size_t payload = n * (4 + 4 + 4 + 1);
+  const size_t need = sizeof(StateHeader) + payload;
+  if (!buf) {
+    *bytes = need;
+    return RFA_OK;
+  }
+  if (*bytes < need) {
+    *bytes = need;
+    return fail(RFA_ERR_ARG, "buffer too small (%zu bytes needed)", need);
+  }
+  uint8_t* out = (uint8_t*)buf;
+  StateHeader h{};
+  std::memcpy(h.magic, "RFASTAT1", 8);
+  h.version = 1;
+  h.nx = g->g.nx;
+  h.ny = g->g.ny;
+  h.nz = g->g.nz;
+  h.steps = g->steps;
+  h.payload = payload;
+  uint8_t* p = out + sizeof h;
+  HIP_TRY(hipMemcpyAsync(p, g->hi[g->cur], n * 4, hipMemcpyDeviceToHost, g->st));
+  HIP_TRY(hipMemcpyAsync(p + n * 4, g->lo[g->cur], n * 4, hipMemcpyDeviceToHost, g->st));
+  HIP_TRY(hipMemcpyAsync(p + n * 8, g->om, n * 4, hipMemcpyDeviceToHost, g->st));
+  HIP_TRY(hipMemcpyAsync(p + n * 12, g->lab, n, hipMemcpyDeviceToHost, g->st));
+  HIP_TRY(hipStreamSynchronize(g->st));
+  h.checksum = fnv1a(p, payload);
+  std::memcpy(out, &h, sizeof h);
+  *bytes = need;
+  return RFA_OK;
+}
+
+rfa_status rfa_load_state(rfa_grid g, const void* buf, size_t bytes) {
+  if (!g || !buf) return fail(RFA_ERR_ARG, "grid and buf are required");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "no tissue");
+  const size_t n = g->g.n();
+  if (bytes < sizeof(StateHeader)) return fail(RFA_ERR_STATE, "state buffer too small");
+  StateHeader h;
+  std::memcpy(&h, buf, sizeof h);
+  const uint8_t* p = (const uint8_t*)buf + sizeof h;
+  if (std::memcmp(h.magic, "RFASTAT1", 8) != 0 || h.version != 1)
+    return fail(RFA_ERR_STATE, "not a state buffer");
+  if (h.nx != g->g.nx || h.ny != g->g.ny || h.nz != g->g.nz || h.payload != n * 13 ||
+      bytes < sizeof h + h.payload)
+    return fail(RFA_ERR_STATE, "state buffer is for another grid shape");
+  if (fnv1a(p, h.payload) != h.checksum) return fail(RFA_ERR_STATE, "state checksum mismatch");
+  // class bits must agree with the current tissue
+  std::vector<uint8_t> cur(n);
+  HIP_TRY(hipMemcpyAsync(cur.data(), g->lab, n, hipMemcpyDeviceToHost, g->st));
+  HIP_TRY(hipStreamSynchronize(g->st));
+  for (size_t i = 0; i < n; ++i)
+    if ((cur[i] & 0x7F) != (p[n * 12 + i] & 0x7F))
+      return fail(RFA_ERR_STATE, "state buffer was saved with different tissue");
+  g->cur = 0;
+  HIP_TRY(hipMemcpyAsync(g->hi[0], p, n * 4, hipMemcpyHostToDevice, g->st));
+  HIP_TRY(hipMemcpyAsync(g->lo[0], p + n * 4, n * 4, hipMemcpyHostToDevice, g->st));
+  HIP_TRY(hipMemcpyAsync(g->om, p + n * 8, n * 4, hipMemcpyHostToDevice, g->st));
+  HIP_TRY(hipMemcpyAsync(g->lab, p + n * 12, n, hipMemcpyHostToDevice, g->st));
+  HIP_TRY(hipStreamSynchronize(g->st));
+  g->steps = h.steps;
+  g->energy_valid = false;
+  return RFA_OK;
+}
+
+rfa_status rfa_get_step_count(rfa_grid g, long long* steps) {
+  if (!g || !steps) return fail(RFA_ERR_ARG, "grid and steps are required");
+  *steps = g->steps;
+  return RFA_OK;
+}
+
+rfa_status rfa_kernel_stats(rfa_grid g, double* kernel_ms, long long* launches,
+                            long long* voxel_steps) {
+  if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
+  if (kernel_ms) *kernel_ms = g->kernel_ms;
+  if (launches) *launches = g->kernel_launches;
+  if (voxel_steps) *voxel_steps = g->kernel_voxel_steps;
+  g->kernel_ms = 0.0;
+  g->kernel_launches = 0;
+  g->kernel_voxel_steps = 0;
+  return RFA_OK;
+}
+
+rfa_status rfa_get_plan(rfa_grid g, int* kernel, int* depth, int* tile_y, int* tile_x,
+                        int* workgroups) {
+  if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
+  if (kernel) *kernel = g->plan.kind;
+  if (depth) *depth = g->plan.depth;
+  if (tile_y) *tile_y = g->plan.ty;
+  if (tile_x) *tile_x = g->plan.xc;
+  if (workgroups) *workgroups = g->plan.nwg;
+  return RFA_OK;
+}
+
+namespace {
+struct TuneKey {
+  int nx, ny, nz, perf;
+  bool operator==(const TuneKey& o) const {
+    return nx == o.nx && ny == o.ny && nz == o.nz && perf == o.perf;
+  }
+};
+std::vector<std::pair<TuneKey, StepPlan>> g_tuned;
+}  // namespace
+
+rfa_status rfa_tune(rfa_grid g, double dt, int reps) {
+  if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "set_tissue before tune");
+  if (!finite_pos(dt) || reps < 1) return fail(RFA_ERR_ARG, "dt > 0 and reps >= 1 required");
+  if (dt > g->dt_max)
+    return fail(RFA_ERR_UNSTABLE, "dt %.6g s exceeds the stability bound %.6g s", dt, g->dt_max);
+  const TuneKey key{g->g.nx, g->g.ny, g->g.nz, g->perf ? 1 : 0};
+  for (auto& kv : g_tuned)
+    if (kv.first == key) {
+      g->plan = kv.second;
+      g->plan_tuned = true;
+      return RFA_OK;
+    }
+  if (dt != g->tab_dt) {
+    build_tables(g, dt);
+    HIP_TRY(hipMemcpyAsync(g->tab_dev, &g->tab_host, sizeof(Tables), hipMemcpyHostToDevice, g->st));
+    HIP_TRY(hipStreamSynchronize(g->st));
+    g->tab_dt = dt;
+  }
+  if (dt != g->src_dt) {
+    HIP_TRY(launch_source_increment(g->g, g->lab, g->q64, g->cp_dev, dt, g->src, g->st));
+    g->src_dt = dt;
+  }
+  const size_t n = g->g.n();
+  float* om2 = nullptr;
+  uint8_t* lab2 = nullptr;
+  rfa_status s;
+  if ((s = dmalloc(&om2, n)) != RFA_OK) return s;
+  if ((s = dmalloc(&lab2, n)) != RFA_OK) { (void)hipFree(om2); return s; }
+  if ((s = ensure_events(g, 2)) != RFA_OK) { (void)hipFree(om2); (void)hipFree(lab2); return s; }
+  StepPlan cand[32];
+  int nc = plan_candidates(g->g, cand, 32);
+  const StepConst K = step_const(g, dt);
+  StepBuffers b;
+  b.hi_in = g->hi[g->cur];
+  b.lo_in = g->lo[g->cur];
+  b.hi_out = g->hi[1 - g->cur];
+  b.lo_out = g->lo[1 - g->cur];
+  b.lab = lab2;
+  b.src = g->src;
+  b.omega = om2;
+  b.perf = g->perf;
+  b.tab = g->tab_dev;
+  b.n_classes = g->n_classes;
+  b.partials = g->partials;
+  double best_ms = 1e300;
+  StepPlan best = g->plan;
+  hipError_t e = hipSuccess;
+  for (int c = 0; c < nc && e == hipSuccess; ++c) {
+    if ((e = hipMemcpyAsync(om2, g->om, n * sizeof(float), hipMemcpyDeviceToDevice, g->st))) break;
+    if ((e = hipMemcpyAsync(lab2, g->lab, n, hipMemcpyDeviceToDevice, g->st))) break;
+    if ((e = launch_plan(g->g, cand[c], b, K, g->st))) break;  // warm-up
+    if ((e = hipEventRecord(g->events[0], g->st))) break;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_plan(g->g, cand[c], b, K, g->st);
+    if (e) break;
+    if ((e = hipEventRecord(g->events[1], g->st))) break;
+    if ((e = hipEventSynchronize(g->events[1]))) break;
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, g->events[0], g->events[1]))) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = cand[c];
+    }
+  }
+  (void)hipStreamSynchronize(g->st);
+  (void)hipFree(om2);
+  (void)hipFree(lab2);
+  if (e != hipSuccess) return fail(RFA_ERR_HIP, "tune failed: %s", hipGetErrorString(e));
+  g->plan = best;
+  g->plan_tuned = true;
+  g_tuned.push_back({key, best});
+  return RFA_OK;
+}
+
+rfa_status rfa_copy_bandwidth(size_t bytes, int reps, double* gbps) {
+  if (!gbps || bytes < 4096 || reps < 1) return fail(RFA_ERR_ARG, "bytes >= 4096, reps >= 1");
+  const size_t n4 = bytes / 2 / sizeof(float4);
+  float4* a = nullptr;
+  float4* b = nullptr;
+  rfa_status s;
+  if ((s = dmalloc(&a, n4)) != RFA_OK) return s;
+  if ((s = dmalloc(&b, n4)) != RFA_OK) { (void)hipFree(a); return s; }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipSuccess;
+  float ms = 0.f;
+  do {
+    if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) break;
+    if ((e = hipMemsetAsync(a, 0, n4 * sizeof(float4), nullptr))) break;
+    if ((e = launch_copy(a, b, n4, nullptr))) break;
+    if ((e = hipEventRecord(e0, nullptr))) break;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(a, b, n4, nullptr);
+    if (e) break;
+    if ((e = hipEventRecord(e1, nullptr)) || (e = hipEventSynchronize(e1))) break;
+    e = hipEventElapsedTime(&ms, e0, e1);
+  } while (false);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  if (e != hipSuccess) return fail(RFA_ERR_HIP, "copy bandwidth: %s", hipGetErrorString(e));
+  *gbps = 2.0 * n4 * sizeof(float4) * reps / (ms * 1e-3) / 1e9;
+  return RFA_OK;
+}
+
+void rfa_destroy_grid(rfa_grid g) {
+  if (!g) return;
+  if (g->st) (void)hipStreamSynchronize(g->st);
+  else (void)hipDeviceSynchronize();
+  free_all(g);
+  delete g;
+}
+
+const char* rfa_status_string(rfa_status s) {
+  switch (s) {
+    case RFA_OK: return "ok";
+    case RFA_ERR_ARG: return "invalid argument";
+    case RFA_ERR_STATE: return "invalid state";
+    case RFA_ERR_UNSTABLE: return "dt above the stability bound";
+    case RFA_ERR_OOM: return "out of device memory";
+    case RFA_ERR_HIP: return "HIP runtime error";
+    case RFA_ERR_NUMERIC: return "non-finite state";
+  }
+  return "unknown status";
+}
+
+const char* rfa_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

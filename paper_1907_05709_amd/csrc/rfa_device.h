@@ -1,0 +1,127 @@
+// rfa_device.h -- device-side definitions shared by the stepper kernels.
+//
+// The state is the excess temperature theta = T - 37 degC held as an
+// unevaluated float-float pair (hi, lo): plain FP32 cannot keep the explicit
+// update's rounding below 1e-4 K at the 700-1500 degC needle-axis
+// temperatures of Gaussian line sources of tens of watts, while the pair
+// carries ~48 bits.  Coefficient tables are float-float as well (their
+// FP32 rounding is coherent over a whole region and would bias the result
+// by ~1 ulp of the peak temperature).  The source increment is FP32.
+//
+// Voxel update (Eq. (CUDAbioheat3d) with per-class conductivity in flux form,
+// Alg. 1 for held voxels), in excess temperature:
+//   theta' = theta + sum_axes [C(l,l-)(theta- - theta) + C(l,l+)(theta+ - theta)]
+//                  - B_l f_p theta + Qs_l + s_p
+// with C(a,b) = dt K_face(a,b) / (rho_a c_a d^2), K_face the harmonic mean,
+// B_l = dt h_l / (rho_l c_l), Qs_l = dt (Q_l + h_l (T_a - 37)) / (rho_l c_l),
+// s_p = dt q_p / (rho c) the RF increment and f_p the optional perfusion
+// multiplier.  Damage (Eq. (eq-tissState), T in Kelvin, left point):
+//   Omega' = min(Omega + dt k_a exp(min(c theta / (T_aK + theta), 80)), cap)
+// with T_aK = 310.15 K, k_a = A exp(-Ea / (R T_aK)), c = Ea / (R T_aK).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rfa {
+
+// Internal label byte: class in bits 0-3, flags above.
+constexpr unsigned kClassMask = 0x0Fu;
+constexpr unsigned kTissue = 0x10u;  // class accumulates damage
+constexpr unsigned kHeld = 0x40u;    // fixed class or outermost layer
+constexpr unsigned kLatch = 0x80u;   // t_death reached (sticky)
+constexpr int kMaxClasses = 16;
+
+// Per-dt coefficient tables, staged into LDS by every work-group.
+struct Tables {
+  float2 cf[3][kMaxClasses * kMaxClasses];  // [axis][a*16+b] = C(a,b) hi/lo
+  float4 cls[kMaxClasses];                  // {B hi, B lo, Qs, rho c V}
+};
+
+// Damage / latch constants of one dt.
+struct StepConst {
+  float dtka;    // dt * k_a
+  float c2;      // c * log2(e)
+  float tak;     // T_aK = 310.15
+  float clamp2;  // 80 * log2(e)
+  float cap;     // Omega cap
+  float thr;     // t_death - 37
+};
+
+// Per-thread diagnostic partials of one step.
+struct Partial {
+  float perf;     // sum rho c V * (B f theta)       -> J removed by perfusion
+  float bnd;      // sum rho c V * conduction term   -> J received from held voxels
+  unsigned mono;  // free voxels whose increment was negative
+};
+
+__device__ __forceinline__ float axis_term(float hi, float lo, float hm, float lm, float hp,
+                                           float lp, float2 cm, float2 cp) {
+  // The two faces of an axis are summed as a pair, products unfused, so that
+  // mirrored inputs give bitwise mirrored outputs.
+  const float dm = (hm - hi) + (lm - lo);
+  const float dp = (hp - hi) + (lp - lo);
+  return (cm.x * dm + cp.x * dp) + (cm.y * dm + cp.y * dp);
+}
+
+// One voxel of one step.  Held voxels pass their own values as neighbours.
+// cf points at the LDS copy of Tables::cf (3 x 256 float2), cls at Tables::cls.
+__device__ __forceinline__ void voxel_step(
+    float hi, float lo, unsigned lab,
+    float hxm, float lxm, unsigned bxm, float hxp, float lxp, unsigned bxp,
+    float hym, float lym, unsigned bym, float hyp, float lyp, unsigned byp,
+    float hzm, float lzm, unsigned bzm, float hzp, float lzp, unsigned bzp,
+    float s, float pf, float& om, const float2* __restrict__ cf,
+    const float4* __restrict__ cls, const StepConst& K,
+    float& nh, float& nl, unsigned& nlab, Partial& acc) {
+  const unsigned l = lab & kClassMask;
+  const float2* cx = cf + l * kMaxClasses;
+  const float2* cy = cx + kMaxClasses * kMaxClasses;
+  const float2* cz = cy + kMaxClasses * kMaxClasses;
+  const float ax = axis_term(hi, lo, hxm, lxm, hxp, lxp, cx[bxm & kClassMask], cx[bxp & kClassMask]);
+  const float ay = axis_term(hi, lo, hym, lym, hyp, lyp, cy[bym & kClassMask], cy[byp & kClassMask]);
+  const float az = axis_term(hi, lo, hzm, lzm, hzp, lzp, cz[bzm & kClassMask], cz[bzp & kClassMask]);
+  const float cond = (ax + ay) + az;
+  const float4 c = cls[l];
+  const float bh = c.x * pf, bl = c.y * pf;
+  const float perf = __builtin_fmaf(bh, hi, __builtin_fmaf(bl, hi, bh * lo));
+  const float inc = (cond - perf) + (c.z + s);
+  // float-float accumulation: (hi, lo) + inc, renormalised
+  const float t = lo + inc;
+  const float s1 = hi + t;
+  const float v = s1 - hi;
+  const float e = (hi - (s1 - v)) + (t - v);
+  const float h2 = s1 + e;
+  const float l2 = e - (h2 - s1);
+  const bool held = (lab & kHeld) != 0u;
+  nh = held ? hi : h2;
+  nl = held ? lo : l2;
+  // Arrhenius increment evaluated at the step's input temperature.
+  float x = K.c2 * hi * __builtin_amdgcn_rcpf(K.tak + hi);
+  x = fminf(x, K.clamp2);
+  const float rate = K.dtka * __builtin_amdgcn_exp2f(x);
+  const bool tissue = (lab & kTissue) != 0u;
+  om = tissue ? fminf(om + rate, K.cap) : om;
+  const bool reached = nh > K.thr || (nh == K.thr && nl >= 0.0f);
+  nlab = (tissue && reached) ? (lab | kLatch) : lab;
+  acc.mono += (!held && inc < 0.0f) ? 1u : 0u;
+  acc.perf = held ? acc.perf : __builtin_fmaf(c.w, perf, acc.perf);
+  acc.bnd = held ? acc.bnd : __builtin_fmaf(c.w, cond, acc.bnd);
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ unsigned wave_sum_u(unsigned v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace rfa

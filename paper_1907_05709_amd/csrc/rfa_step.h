@@ -1,0 +1,59 @@
+// rfa_step.h -- step scheduling: kernel choice, launch shape, launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rfa.h"
+#include "rfa_kernels.h"
+#include "rfa_tiled.h"
+
+namespace rfa {
+
+constexpr int kMaxDepth = 1;
+
+enum StepKind { kStepNaive = 1, kStepTiled = 2 };
+
+struct StepPlan {
+  int kind;    // StepKind
+  int depth;   // steps per launch
+  int ty;      // tile rows (y) per work-group (tiled)
+  int xc;      // x planes per work-group (tiled)
+  int nwg;     // work-groups per launch (stride of the partials)
+};
+
+StepPlan plan_naive(Grid3 g);
+StepPlan plan_tiled(Grid3 g, int ty, int xc);
+// Heuristic plan from the options (kernel, tile_y, tile_x; 0 = automatic).
+StepPlan plan_default(Grid3 g, int kernel, int tile_y, int tile_x);
+// Candidate plans for tuning.
+int plan_candidates(Grid3 g, StepPlan* out, int max_out);
+// Largest partial stride any plan of this grid can need.
+int plan_max_wg(Grid3 g);
+
+struct StepState {
+  float** hi;       // [2] ping-pong
+  float** lo;       // [2]
+  int* cur;         // index of the current image
+  uint8_t* lab;
+  const float* src;
+  float* om;
+  const float* perf;
+  const Tables* tab;
+  int n_classes;
+};
+
+// One launch of the plan reading image `in` and writing image `out`.
+hipError_t launch_plan(Grid3 g, const StepPlan& plan, const StepBuffers& b, const StepConst& K,
+                       hipStream_t st);
+
+// Advance n_steps.  partials (nullable) has room for `slots` launches and is
+// folded into dacc[3] every `slots` launches and at the end.  If events is
+// not null, each block of `period` consecutive launches (the last one may be
+// shorter) is bracketed by the event pair events[2j], events[2j+1]
+// (j = 0, 1, ...; *n_timed receives the number of blocks).
+rfa_status run_steps(Grid3 g, const StepPlan& plan, StepState& s, const StepConst& K,
+                     int n_steps, float* partials, int slots, double* dacc,
+                     hipEvent_t* events, int period, int* n_timed, hipStream_t st);
+
+}  // namespace rfa

@@ -1,0 +1,321 @@
+// rfa_tiled.hip -- the production step kernel: 2.5-D tiles marching along x.
+//
+// A work-group of TY wavefronts owns a tile of 64 (z, one voxel per lane)
+// by TY (y, one row per wave) voxel columns and marches along x over a
+// chunk of xc planes.  The y and z neighbours of plane x come from a
+// double-buffered LDS copy of the plane with a one-voxel halo; the x
+// neighbours from registers.  Each voxel's state is read from HBM once per
+// step, plus the halo ring of the tile.
+//
+// Latency hiding: the loads of plane x + kAhead (own column, halo element,
+// source increment, damage integral) are issued while plane x is computed,
+// into a ring of kSlots register sets.  The x loop is unrolled kSlots times
+// so every ring index is a compile-time constant (no register moves).  One
+// barrier per plane.
+//
+// Addressing: every array is accessed through a buffer descriptor whose
+// base is the first plane the work-group touches; a lane adds a fixed
+// 32-bit byte offset (its column) and the plane enters as a uniform scalar
+// offset, so loads and stores cost no vector address arithmetic.  Lanes
+// whose column lies outside the grid read the grid's (0, 0) column, which
+// is on the held outer layer, and store nothing.
+//
+// Work-group ids are remapped so consecutive tiles on one XCD are spatial
+// neighbours and share their halo rows in that XCD's L2.
+//
+// The per-voxel arithmetic is voxel_step() of rfa_device.h, identical to
+// the reference kernel, so both produce bitwise-equal states.  A held
+// voxel's result does not depend on its neighbours, so held and free voxels
+// share one instruction stream.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "rfa_tiled.h"
+
+namespace rfa {
+
+namespace {
+
+constexpr int kAhead = 3;           // planes in flight ahead of the computed one
+constexpr int kSlots = kAhead + 1;  // register ring size
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9 buffer descriptor word 3 (32-bit data format)
+
+__device__ __forceinline__ int remap_xcd(int wg, int nwg) {
+  // Hardware places work-group w on XCD w % 8.  Give XCD k the contiguous
+  // range of logical tiles [base_k, base_k + count_k).
+  constexpr int kXcd = 8;
+  const int per = nwg / kXcd;
+  const int rem = nwg % kXcd;
+  const int xcd = wg % kXcd;
+  const int slot = wg / kXcd;
+  const int base = xcd * per + (xcd < rem ? xcd : rem);
+  return base + slot;
+}
+
+// Registers of one plane for one thread.
+struct Plane {
+  float h, l;       // own column state
+  unsigned b;       // own column label byte
+  float hh, hl;     // halo element state
+  unsigned hb;      // halo element label byte
+  float s, om, pf;  // own voxel: source increment, damage integral, perfusion factor
+};
+
+// Buffer descriptors of the arrays, based at plane xb of the grid.
+struct Rsrc {
+  __amdgpu_buffer_rsrc_t hi_in, lo_in, lab, src, om, perf, hi_out, lo_out;
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, size_t bytes) {
+  const int n = bytes > 0x7fffffffu ? 0x7fffffff : (int)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, kRsrcWord3);
+}
+
+// 32-bit buffer loads/stores move raw bits: reinterpret, never convert.
+__device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
+}
+__device__ __forceinline__ void st_f32(float v, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                       int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, soff, 0);
+}
+__device__ __forceinline__ unsigned ld_u8(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+  return (unsigned)__builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, soff, 0);
+}
+
+struct TileCtx {
+  Rsrc r;
+  int xb;            // first plane covered by the descriptors
+  int nx, x1;
+  unsigned psz;      // plane size, voxels
+  unsigned col;      // own column offset (voxels) in a plane
+  unsigned hoff;     // halo element offset (voxels) in a plane
+};
+
+template <bool PERF>
+__device__ __forceinline__ void load_plane(const TileCtx& c, int x, Plane& q) {
+  const int xo = min(x, c.nx - 1) - c.xb;   // uniform
+  const int xf = min(x, c.x1 - 1) - c.xb;   // uniform
+  const int so4 = xo * (int)c.psz * 4, so1 = xo * (int)c.psz;
+  const int sf4 = xf * (int)c.psz * 4, sf1 = xf * (int)c.psz;
+  q.h = ld_f32(c.r.hi_in, c.col * 4, so4);
+  q.l = ld_f32(c.r.lo_in, c.col * 4, so4);
+  q.b = ld_u8(c.r.lab, c.col, so1);
+  q.s = ld_f32(c.r.src, c.col * 4, sf4);
+  q.om = ld_f32(c.r.om, c.col * 4, sf4);
+  q.pf = PERF ? ld_f32(c.r.perf, c.col * 4, sf4) : 1.0f;
+  q.hh = ld_f32(c.r.hi_in, c.hoff * 4, sf4);
+  q.hl = ld_f32(c.r.lo_in, c.hoff * 4, sf4);
+  q.hb = ld_u8(c.r.lab, c.hoff, sf1);
+}
+
+}  // namespace
+
+template <int TY, bool PERF>
+__global__ __launch_bounds__(64 * TY) void k_step_tiled(StepBuffers b, StepConst K, int nx,
+                                                        int ny, int nz, int xc, int tiles_z,
+                                                        int tiles_y, int nwg) {
+  constexpr int W = 66;             // 64 lanes + z halo
+  constexpr int ROWS = TY + 2;      // TY rows + y halo
+  constexpr int CELLS = ROWS * W;   // plus one scratch cell for threads without halo
+  constexpr int NT = 64 * TY;
+  __shared__ float2 cf[3 * kMaxClasses * kMaxClasses];
+  __shared__ float4 cls[kMaxClasses];
+  __shared__ float2 ts[2][CELLS + 1];
+  __shared__ uint8_t bs[2][CELLS + 1];
+  __shared__ float red[3][TY];
+
+  const int lane = threadIdx.x & 63;
+  const int wy = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  {
+    // stage the coefficient tables of the classes in use
+    const int nc = b.n_classes;
+    const int per_axis = nc * nc;
+    const float2* src = &b.tab->cf[0][0];
+    for (int t = tid; t < 3 * per_axis; t += NT) {
+      const int ax = t / per_axis, r = t - ax * per_axis;
+      const int a = r / nc, c = r - a * nc;
+      const int i = ax * kMaxClasses * kMaxClasses + a * kMaxClasses + c;
+      cf[i] = src[i];
+    }
+    if (tid < nc) cls[tid] = b.tab->cls[tid];
+  }
+
+  const int wg = remap_xcd(blockIdx.x, nwg);
+  const int tz = wg % tiles_z;
+  const int ty = (wg / tiles_z) % tiles_y;
+  const int tx = wg / (tiles_z * tiles_y);
+  const int z = tz * 64 + lane;
+  const int y = ty * TY + wy;
+  const int x0 = tx * xc;
+  const bool inside = z < nz && y < ny;
+
+  TileCtx c;
+  c.nx = nx;
+  c.x1 = min(x0 + xc, nx);
+  c.xb = max(x0 - 1, 0);
+  c.psz = (unsigned)(ny * nz);
+  c.col = inside ? (unsigned)(y * nz + z) : 0u;
+  {
+    const size_t off = (size_t)c.xb * c.psz;
+    const size_t rest = (size_t)(nx - c.xb) * c.psz;
+    c.r.hi_in = make_rsrc(b.hi_in + off, rest * 4);
+    c.r.lo_in = make_rsrc(b.lo_in + off, rest * 4);
+    c.r.lab = make_rsrc(b.lab + off, rest);
+    c.r.src = make_rsrc(b.src + off, rest * 4);
+    c.r.om = make_rsrc(b.omega + off, rest * 4);
+    c.r.perf = make_rsrc(PERF ? b.perf + off : b.src + off, rest * 4);
+    c.r.hi_out = make_rsrc(b.hi_out + off, rest * 4);
+    c.r.lo_out = make_rsrc(b.lo_out + off, rest * 4);
+  }
+
+  // Halo element owned by this thread (at most one): y rows y0-1 / y0+TY,
+  // z columns z0-1 / z0+64.  Threads without one write a scratch cell.
+  int hcell = CELLS, hy = -1, hz = -1;
+  {
+    const int y0 = ty * TY, z0 = tz * 64;
+    int hrow = 0, hcol = 0;
+    if (tid < 64) {
+      hrow = 0; hcol = tid + 1; hy = y0 - 1; hz = z0 + tid;
+    } else if (tid < 128) {
+      hrow = TY + 1; hcol = tid - 64 + 1; hy = y0 + TY; hz = z0 + tid - 64;
+    } else if (tid < 128 + TY) {
+      hrow = tid - 128 + 1; hcol = 0; hy = y0 + tid - 128; hz = z0 - 1;
+    } else if (tid < 128 + 2 * TY) {
+      hrow = tid - 128 - TY + 1; hcol = 65; hy = y0 + tid - 128 - TY; hz = z0 + 64;
+    }
+    if (hy >= 0 && hy < ny && hz >= 0 && hz < nz) hcell = hrow * W + hcol;
+  }
+  c.hoff = hcell < CELLS ? (unsigned)(hy * nz + hz) : c.col;
+
+  // x-1 neighbour of the plane being computed (own column)
+  float hm, lm;
+  unsigned bm;
+  {
+    const int so = (max(x0 - 1, 0) - c.xb) * (int)c.psz;
+    hm = ld_f32(c.r.hi_in, c.col * 4, so * 4);
+    lm = ld_f32(c.r.lo_in, c.col * 4, so * 4);
+    bm = ld_u8(c.r.lab, c.col, so);
+  }
+  Plane q[kSlots];
+#pragma unroll
+  for (int k = 0; k < kAhead; ++k) load_plane<PERF>(c, x0 + k, q[k]);
+
+  Partial acc{0.0f, 0.0f, 0u};
+  const int me = (wy + 1) * W + lane + 1;  // own LDS cell
+
+  // One plane; S = ring slot of plane x (compile time), BUF = LDS buffer.
+  auto plane_step = [&](auto S_, auto BUF_, int x) {
+    constexpr int S = decltype(S_)::value;
+    constexpr int BUF = decltype(BUF_)::value;
+    constexpr int SN = (S + 1) % kSlots;       // plane x+1
+    constexpr int SL = (S + kAhead) % kSlots;  // slot receiving plane x+kAhead
+    load_plane<PERF>(c, x + kAhead, q[SL]);
+    const Plane& P = q[S];
+    ts[BUF][me] = make_float2(P.h, P.l);
+    bs[BUF][me] = (uint8_t)P.b;
+    ts[BUF][hcell] = make_float2(P.hh, P.hl);
+    bs[BUF][hcell] = (uint8_t)P.hb;
+    __syncthreads();
+    const float2 ym = ts[BUF][me - W], yp = ts[BUF][me + W];
+    const float2 zm = ts[BUF][me - 1], zp = ts[BUF][me + 1];
+    const unsigned bym = bs[BUF][me - W], byp = bs[BUF][me + W];
+    const unsigned bzm = bs[BUF][me - 1], bzp = bs[BUF][me + 1];
+    const Plane& N = q[SN];
+    float nh, nl, om = P.om;
+    unsigned nlab;
+    voxel_step(P.h, P.l, P.b, hm, lm, bm, N.h, N.l, N.b, ym.x, ym.y, bym, yp.x, yp.y, byp,
+               zm.x, zm.y, bzm, zp.x, zp.y, bzp, P.s, P.pf, om, cf, cls, K, nh, nl, nlab, acc);
+    if (inside) {
+      const int so = (x - c.xb) * (int)c.psz;  // uniform
+      st_f32(nh, c.r.hi_out, c.col * 4, so * 4);
+      st_f32(nl, c.r.lo_out, c.col * 4, so * 4);
+      st_f32(om, c.r.om, c.col * 4, so * 4);
+      if (nlab != P.b)
+        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)nlab, c.r.lab, (int)c.col, so, 0);
+    }
+    hm = P.h;
+    lm = P.l;
+    bm = P.b;
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  static_assert(kSlots == 4, "unrolled for a ring of four planes");
+  // kSlots is even, so plane x uses LDS buffer (x - x0) & 1 = slot & 1.
+  for (int x = x0; x < c.x1; x += kSlots) {
+    plane_step(I0{}, I0{}, x);
+    if (x + 1 < c.x1) plane_step(I1{}, I1{}, x + 1);
+    if (x + 2 < c.x1) plane_step(I2{}, I0{}, x + 2);
+    if (x + 3 < c.x1) plane_step(I3{}, I1{}, x + 3);
+  }
+
+  if (b.partials) {
+    const float pe = wave_sum(acc.perf);
+    const float bn = wave_sum(acc.bnd);
+    const unsigned mo = wave_sum_u(acc.mono);
+    if (lane == 0) {
+      red[0][wy] = pe;
+      red[1][wy] = bn;
+      red[2][wy] = (float)mo;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+      for (int w = 0; w < TY; ++w) {
+        a0 += red[0][w];
+        a1 += red[1][w];
+        a2 += red[2][w];
+      }
+      float* out = b.partials + (size_t)wg * 3;
+      out[0] = a0;
+      out[1] = a1;
+      out[2] = a2;
+    }
+  }
+}
+
+TiledShape tiled_shape(Grid3 g, int ty, int xc) {
+  TiledShape s;
+  s.ty = ty;
+  s.xc = xc;
+  s.tiles_z = (g.nz + 63) / 64;
+  s.tiles_y = (g.ny + ty - 1) / ty;
+  s.chunks_x = (g.nx + xc - 1) / xc;
+  s.nwg = s.tiles_z * s.tiles_y * s.chunks_x;
+  return s;
+}
+
+bool tiled_fits(Grid3 g, int xc) {
+  // scalar plane offsets are signed 32-bit byte offsets from the chunk base
+  return (double)(xc + kAhead + 2) * g.ny * g.nz * 4.0 < 2147483647.0;
+}
+
+template <int TY>
+static hipError_t launch_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
+                            const StepConst& K, hipStream_t st) {
+  dim3 grid(s.nwg), block(64 * TY);
+  if (b.perf)
+    hipLaunchKernelGGL((k_step_tiled<TY, true>), grid, block, 0, st, b, K, g.nx, g.ny, g.nz,
+                       s.xc, s.tiles_z, s.tiles_y, s.nwg);
+  else
+    hipLaunchKernelGGL((k_step_tiled<TY, false>), grid, block, 0, st, b, K, g.nx, g.ny, g.nz,
+                       s.xc, s.tiles_z, s.tiles_y, s.nwg);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_tiled(const TiledShape& s, Grid3 g, const StepBuffers& b,
+                             const StepConst& K, hipStream_t st) {
+  if (!tiled_fits(g, s.xc)) return hipErrorInvalidValue;
+  switch (s.ty) {
+    case 4: return launch_ty<4>(s, g, b, K, st);
+    case 8: return launch_ty<8>(s, g, b, K, st);
+    case 16: return launch_ty<16>(s, g, b, K, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace rfa

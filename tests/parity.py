@@ -1,0 +1,64 @@
+"""GPU-vs-oracle comparison rules (test helpers).
+
+Tolerances (FP32 float-float GPU state against the FP64 oracle):
+  * temperature: max |T_gpu - T_oracle| <= 1e-4 K over all voxels;
+  * latch mask (bit0) identical wherever |Tmax_oracle - t_death| >= 1e-3 K;
+  * damage mask (bit1) identical wherever |ln Omega_oracle| >= 1e-3;
+  * damage integral within 2e-3 relative where Omega_oracle >= 1e-6 (FP32
+    accumulation of up to 6000 left-point increments plus the 1e-4 K
+    temperature budget times d ln(rate)/dT ~ 0.3 /K);
+  * per-class dead volumes within the voxels inside the margins.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+T_TOL = 1e-4
+T_MARGIN = 1e-3
+LN_MARGIN = 1e-3
+OMEGA_RTOL = 2e-3
+
+
+def gpu_run(case, n_steps=None, depth=0, device=False, diag=True, dt=None, kernel=0,
+            tile_y=0, tile_x=0):
+    from paper_1907_05709_amd import rfa
+    g = rfa.Grid(case.shape, case.spacing, device=device, depth=depth, kernel=kernel,
+                 tile_y=tile_y, tile_x=tile_x,
+                 t_death=case.t_death, A=case.arrhenius_a, Ea=case.arrhenius_ea,
+                 R=case.gas_r, omega_cap=case.omega_cap)
+    g.load_case(case)
+    d = g.step(case.n_steps if n_steps is None else n_steps, case.dt if dt is None else dt,
+               diag=diag)
+    T = g.temperature()
+    mask, om, dead = g.damage()
+    if device:
+        T, mask, om = T.cpu().numpy(), mask.cpu().numpy(), om.cpu().numpy()
+    return g, T, mask, om, dead, d
+
+
+def compare(case, T_gpu, mask_gpu, om_gpu, ost, t_tol=T_TOL):
+    """Assert the parity rules against an oracle State; returns max |dT|."""
+    dT = np.abs(T_gpu - ost.T)
+    err = float(dT.max())
+    assert err <= t_tol, f"max|dT| = {err:.3e} K at {np.unravel_index(dT.argmax(), dT.shape)}"
+    m_or = ost.masks(case)
+    safe0 = np.abs(ost.tmax - case.t_death) >= T_MARGIN
+    with np.errstate(divide="ignore"):
+        safe1 = np.abs(np.log(np.maximum(ost.omega, 1e-300))) >= LN_MARGIN
+    b0 = (mask_gpu & 1) != (m_or & 1)
+    b1 = (mask_gpu & 2) != (m_or & 2)
+    assert not (b0 & safe0).any(), f"{int((b0 & safe0).sum())} latch mismatches outside margin"
+    assert not (b1 & safe1).any(), f"{int((b1 & safe1).sum())} damage mismatches outside margin"
+    big = ost.omega >= 1e-6
+    rel = np.abs(om_gpu[big].astype(np.float64) - ost.omega[big]) / ost.omega[big]
+    assert rel.size == 0 or rel.max() <= OMEGA_RTOL, f"Omega rel err {rel.max():.3e}"
+    return err
+
+
+def dead_counts(case, mask):
+    out = np.zeros((len(case.tissue), 2), dtype=np.int64)
+    for c in range(len(case.tissue)):
+        sel = case.labels == c
+        out[c, 0] = int(((mask & 1) != 0)[sel].sum())
+        out[c, 1] = int(((mask & 2) != 0)[sel].sum())
+    return out

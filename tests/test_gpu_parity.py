@@ -1,0 +1,211 @@
+"""GPU (HIP, through the C ABI) against the FP64 oracle on the same seeded
+inputs.  Rules are in parity.py: max|dT| <= 1e-4 K, masks identical outside
+a 1e-3 K / 1e-3 ln-Omega margin, damage integral within 2e-3 relative."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import parity
+from oracle import oracle as O
+from paper_1907_05709_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle_built():
+    O.build(force=False)
+
+
+def _diag_sums(dg):
+    return dict(injected=dg[:, 1].sum(), perfusion=dg[:, 2].sum(), boundary=dg[:, 3].sum(),
+                mono=dg[:, 5].sum(), energy=dg[-1, 0], tmax=dg[-1, 7], tmin=dg[-1, 6])
+
+
+def _check_diag(d, od, rtol=2e-5):
+    scale = abs(od["injected"]) + abs(od["perfusion"]) + abs(od["boundary"])
+    assert math.isclose(d["injected_J"], od["injected"], rel_tol=1e-9)
+    assert math.isclose(d["energy_J"], od["energy"], rel_tol=rtol)
+    assert abs(d["perfusion_J"] - od["perfusion"]) <= rtol * scale
+    assert abs(d["boundary_J"] - od["boundary"]) <= rtol * scale
+    assert abs(d["residual_J"]) <= 1e-5 * scale
+    assert math.isclose(d["t_max_C"], od["tmax"], abs_tol=1e-4)
+    assert math.isclose(d["t_min_C"], od["tmin"], abs_tol=1e-4)
+
+
+def test_homogeneous_32cube_full_run():
+    """32^3, 1 mm, 20 W straight line source, 1000 x 0.05 s."""
+    case = W.case_homogeneous()
+    ost, dg, _ = O.run(case, diag=True)
+    g, T, mask, om, dead, d = parity.gpu_run(case)
+    err = parity.compare(case, T, mask, om, ost)
+    print(f"homogeneous 32^3: max|dT| = {err:.3e} K, Tmax = {T.max():.3f}")
+    _check_diag(d, _diag_sums(dg))
+    assert d["mono_violations"] == 0
+    V = np.prod(case.spacing)
+    cnt = parity.dead_counts(case, ost.masks(case))
+    assert np.allclose(dead[: len(case.tissue)], cnt * V, rtol=0, atol=2 * V)
+    g.close()
+
+
+def test_homogeneous_mirror_symmetry():
+    case = W.case_homogeneous(n_steps=300)
+    g, T, mask, om, dead, d = parity.gpu_run(case)
+    for other in (T[::-1], T[:, ::-1], T[:, :, ::-1], T.transpose(1, 0, 2)):
+        assert np.abs(other - T).max() <= 1e-6
+    g.close()
+
+
+@pytest.mark.parametrize("seed,shape", [(31, (37, 29, 70)), (32, (5, 66, 131)),
+                                        (33, (23, 9, 3 + 64))])
+def test_random_heterogeneous_ragged(seed, shape):
+    """Random classes (incl. a held class at a random temperature and Q_m),
+    anisotropic spacing, multi-chord tines, ragged tile tails."""
+    case = W.random_tissue_case(seed, shape=shape, n_classes=6, n_tines=3, n_steps=150)
+    ost, dg, _ = O.run(case, diag=True)
+    g, T, mask, om, dead, d = parity.gpu_run(case)
+    parity.compare(case, T, mask, om, ost)
+    _check_diag(d, _diag_sums(dg))
+    g.close()
+
+
+def test_straight_recipe_64cube():
+    """Heterogeneous liver / tumour / vessels, straight needle, 1000 x 0.01 s."""
+    case = W.case_straight(n=64, seed=2002)
+    ost, dg, _ = O.run(case, diag=True)
+    g, T, mask, om, dead, d = parity.gpu_run(case)
+    err = parity.compare(case, T, mask, om, ost)
+    print(f"straight 64^3: max|dT| = {err:.3e} K, Tmax = {T.max():.2f}")
+    _check_diag(d, _diag_sums(dg))
+    g.close()
+
+
+def test_straight_recipe_full_128cube():
+    """Full-size single-instance workload (128^3 at 0.5 mm, 1000 steps)."""
+    case = W.case_straight()
+    ost, dg, _ = O.run(case, diag=True)
+    g, T, mask, om, dead, d = parity.gpu_run(case)
+    err = parity.compare(case, T, mask, om, ost)
+    print(f"straight 128^3: max|dT| = {err:.3e} K, Tmax = {T.max():.2f}")
+    _check_diag(d, _diag_sums(dg))
+    assert d["mono_violations"] == 0
+    g.close()
+
+
+def test_device_pointers_match_host_pointers():
+    import torch
+    case = W.case_straight(n=40, n_steps=200, seed=2003)
+    g1, T1, m1, o1, _, d1 = parity.gpu_run(case, device=False)
+    g2, T2, m2, o2, _, d2 = parity.gpu_run(case, device=True)
+    assert np.array_equal(T1, T2) and np.array_equal(m1, m2) and np.array_equal(o1, o2)
+    assert d1 == d2
+    torch.cuda.synchronize()
+    g1.close()
+    g2.close()
+
+
+def test_resume_from_saved_state_is_bitwise():
+    case = W.case_straight(n=48, n_steps=0, seed=2004)
+    g, _, _, _, _, _ = parity.gpu_run(case, n_steps=150, diag=False)
+    blob = g.save_state()
+    g.step(120, case.dt, diag=False)
+    T1 = g.temperature()
+    m1, o1, _ = g.damage()
+    g.load_state(blob)
+    assert g.step_count() == 150
+    g.step(60, case.dt, diag=False)
+    g.step(60, case.dt, diag=False)
+    T2 = g.temperature()
+    m2, o2, _ = g.damage()
+    assert np.array_equal(T1, T2) and np.array_equal(m1, m2) and np.array_equal(o1, o2)
+    bad = bytearray(blob)
+    bad[len(bad) // 2] ^= 0xFF
+    from paper_1907_05709_amd import rfa
+    with pytest.raises(rfa.RfaError) as e:
+        g.load_state(bytes(bad))
+    assert e.value.status == rfa.RFA_ERR_STATE
+    g.close()
+
+
+def test_error_codes_leave_state_unchanged():
+    from paper_1907_05709_amd import rfa
+    case = W.case_homogeneous(n=16, n_steps=10)
+    g = rfa.Grid(case.shape, case.spacing)
+    with pytest.raises(rfa.RfaError) as e:
+        g.step(1, 0.05)
+    assert e.value.status == rfa.RFA_ERR_STATE
+    g.load_case(case)
+    g.step(10, case.dt)
+    T0 = g.temperature()
+    dtm = g.dt_max()
+    assert math.isclose(dtm, O.dt_max(case), rel_tol=1e-12)
+    with pytest.raises(rfa.RfaError) as e:
+        g.step(5, dtm * 1.01)
+    assert e.value.status == rfa.RFA_ERR_UNSTABLE
+    bad = case.labels.copy()
+    bad[3, 3, 3] = 7
+    with pytest.raises(rfa.RfaError) as e:
+        g.set_tissue(bad, case.tissue)
+    assert e.value.status == rfa.RFA_ERR_ARG
+    nd = case.needle
+    nd_bad = W.Needle(nd.pt_offset, nd.pts, np.array([float("nan")]), nd.sigma)
+    with pytest.raises(rfa.RfaError) as e:
+        g.set_needle(nd_bad)
+    assert e.value.status == rfa.RFA_ERR_ARG
+    assert np.array_equal(g.temperature(), T0)
+    g.step(1, case.dt)          # still usable with the old needle
+    g.close()
+
+
+@pytest.mark.parametrize("shape,ty,xc", [((40, 37, 70), 4, 3), ((33, 70, 129), 8, 5),
+                                         ((21, 45, 64), 16, 7), ((64, 64, 64), 8, 64)])
+def test_tiled_kernel_bitwise_equals_reference(shape, ty, xc):
+    """The tiled 2.5-D kernel and the one-thread-per-voxel reference share
+    the voxel arithmetic: states, damage and latches must be identical."""
+    case = W.random_tissue_case(40 + ty, shape=shape, n_classes=5, n_tines=2, n_steps=60)
+    _, T1, m1, o1, _, d1 = parity.gpu_run(case, kernel=1)
+    g2, T2, m2, o2, _, d2 = parity.gpu_run(case, kernel=2, tile_y=ty, tile_x=xc)
+    plan = g2.plan()
+    assert plan["kernel"] == 2 and plan["tile_y"] == ty and plan["tile_x"] == min(xc, shape[0])
+    assert np.array_equal(T1, T2) and np.array_equal(m1, m2) and np.array_equal(o1, o2)
+    assert d1["mono_violations"] == d2["mono_violations"]
+    for k in ("perfusion_J", "boundary_J", "energy_J"):
+        assert math.isclose(d1[k], d2[k], rel_tol=1e-5, abs_tol=1e-9)
+    g2.close()
+
+
+def test_tune_keeps_state_and_timing_counts_launches():
+    from paper_1907_05709_amd import rfa
+    case = W.case_straight(n=48, n_steps=20, seed=2005)
+    g = rfa.Grid(case.shape, case.spacing, time_kernels=True)
+    g.load_case(case)
+    g.step(5, case.dt)
+    T0 = g.temperature()
+    m0, o0, _ = g.damage()
+    plan = g.tune(case.dt, reps=3)
+    assert plan["kernel"] in (1, 2)
+    assert np.array_equal(g.temperature(), T0)
+    m1, o1, _ = g.damage()
+    assert np.array_equal(m0, m1) and np.array_equal(o0, o1)
+    g.kernel_stats()
+    g.step(7, case.dt, diag=False)
+    ms, n, vs = g.kernel_stats()
+    assert n == 7 and vs == 7 * case.n_voxels and ms > 0.0
+    assert rfa.rfa_copy_bandwidth(1 << 26, 3) > 100.0
+    g.close()
+
+
+def test_arrhenius_constant_temperature_gpu():
+    """Held tissue voxel at 60 degC: Omega = n dt A exp(-Ea/(R T_K))."""
+    case = W.case_homogeneous(n=8, n_steps=400, dt=0.01)
+    case.tissue.append(W.Tissue(0.52, 1060, 3600, 0, 0, 60.0, fixed=1, tissue=1))
+    case.labels[4, 4, 4] = 2
+    g, T, mask, om, dead, d = parity.gpu_run(case)
+    expect = 400 * 0.01 * case.arrhenius_a * math.exp(-case.arrhenius_ea /
+                                                       (case.gas_r * 333.15))
+    assert math.isclose(float(om[4, 4, 4]), expect, rel_tol=1e-4)
+    assert mask[4, 4, 4] == 3
+    g.close()
