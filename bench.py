@@ -36,8 +36,9 @@ BYTES_PER_VOXEL_STEP = 29
 HBM_PEAK_GBPS = 8000.0
 TIME_PERIOD = 16          # HIP-event-time every 16th step-kernel launch
 KERNEL_SOURCES = ("paper_1907_05709_amd/csrc/rfa_tiled.hip",
+                  "paper_1907_05709_amd/csrc/rfa_tiled.h",
                   "paper_1907_05709_amd/csrc/rfa_device.h",
-                  "paper_1907_05709_amd/csrc/rfa_kernels.hip")
+                  "paper_1907_05709_amd/csrc/rfa_kernels.h")
 
 
 def kernel_hash() -> str:
@@ -115,6 +116,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.config == 4:
+        return bench_batch(args)
     case, name = workload(args.config)
     if args.time_steps > 0:
         case.n_steps = args.time_steps
@@ -173,6 +176,81 @@ def main():
         if steps <= 0:
             steps = max(2, min(case.n_steps, int(2.0e9 / case.n_voxels)))
         out["cpu_baseline"] = cpu_baseline(case, steps)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """Planning sweep: 64 uneven grids (64^3..160^3, 0.5..1 mm, own needle,
+    dt = 0.01 s (dx / 0.5 mm)^2), 2000 steps each; one bench step is one
+    batched call advancing every grid by its 2000 steps.  The plain stepper
+    (each grid stepped on its own, one after another) is timed beside it."""
+    import torch
+    from paper_1907_05709_amd import rfa
+    from paper_1907_05709_amd import workloads as W
+
+    n_steps = args.time_steps if args.time_steps > 0 else 2000
+    cases = W.planning_sweep(64, n_steps=n_steps)
+    grids = []
+    for c in cases:
+        g = rfa.Grid(c.shape, c.spacing)
+        g.load_case(c)
+        grids.append(g)
+    total_vox = sum(c.n_voxels for c in cases)
+    # plain stepper: every grid on its own, one after another
+    for g, c in zip(grids, cases):
+        g.step(min(n_steps, 20), c.dt, diag=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g, c in zip(grids, cases):
+        g.step(n_steps, c.dt, diag=False)
+    torch.cuda.synchronize()
+    seq_wall = time.perf_counter() - t0
+    seq_value = total_vox * n_steps / seq_wall / 1e9
+
+    b = rfa.Batch(grids, [c.dt for c in cases])
+    for _ in range(args.warmup):
+        b.step(n_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev_ms = 0.0
+    for _ in range(args.steps):
+        b.step(n_steps)
+        ms, _ = b.last_time()
+        dev_ms += ms
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = total_vox * n_steps * args.steps / wall / 1e9
+    avg_launch_ms = dev_ms / (args.steps * n_steps)
+    bytes_per_launch = BYTES_PER_VOXEL_STEP * total_vox
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    b.close()
+    for g in grids:
+        g.close()
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GVoxel-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"planning sweep: 64 grids 64^3..160^3 @0.5..1 mm, straight / "
+                               f"3-tine / 9-tine needles, {n_steps} steps each, per-grid dt "
+                               f"(seeds 4000..4063)",
+                   "voxels": total_vox, "time_steps": n_steps,
+                   "plain_stepper_GVox_s": round(seq_value, 3),
+                   "batched_speedup_vs_plain": round(value / seq_value, 3)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "kernel": "k_step_batch",
+                     "avg_launch_us": round(avg_launch_ms * 1e3, 3),
+                     "bytes_per_launch": bytes_per_launch},
+    }
     print(json.dumps(out), flush=True)
 
 

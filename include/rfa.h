@@ -208,6 +208,73 @@ rfa_status rfa_tune(rfa_grid g, double dt, int reps);
  * (read + write counted), GB/s: the achievable HBM ceiling on this device. */
 rfa_status rfa_copy_bandwidth(size_t bytes, int reps, double* gbps);
 
+/* ---- Differentiation -------------------------------------------------------
+ * The damage integral after N steps, Omega^N (Eq. (eq-tissState) summed by
+ * the stepper), is a differentiable function of the tine powers and of the
+ * perfusion field.  rfa_forward_checkpointed runs the forward keeping the
+ * temperature state every ckpt_every steps; rfa_adjoint then runs the exact
+ * discrete adjoint of those steps backwards (recomputing each segment from
+ * its checkpoint, bitwise as in the forward) for a loss whose gradient with
+ * respect to Omega^N is given.  The adjoint differentiates the damage rate
+ * where its exponent cap is inactive and voxels whose Omega^N reached the
+ * cap not at all; latches are not differentiable and do not enter. */
+
+/* Perfusion multiplier f = exp(sum_j B_j(x) ctrl_j) from a uniform cubic
+ * B-spline lattice of m x m x m control values spanning the grid (voxel i of
+ * n along an axis sits at spline coordinate i (m - 3) / (n - 1)); ctrl is a
+ * host float array [m][m][m], m in 4..64, |ctrl| <= 30.  Replaces any
+ * rfa_set_perfusion field. */
+rfa_status rfa_set_perfusion_bspline(rfa_grid g, int m, const float* ctrl);
+
+/* Back to the state rfa_set_tissue creates (temperature, damage, latches,
+ * step count); tissue, needle and perfusion are kept. */
+rfa_status rfa_reset_state(rfa_grid g);
+
+/* New tine powers (W, [n_tines]) for the current needle geometry. */
+rfa_status rfa_set_tine_powers(rfa_grid g, const double* power);
+
+/* n_steps forward steps (as rfa_step) keeping the state at steps
+ * 0, ckpt_every, 2 ckpt_every, ... for rfa_adjoint. */
+rfa_status rfa_forward_checkpointed(rfa_grid g, int n_steps, double dt, int ckpt_every);
+
+/* Adjoint of the last rfa_forward_checkpointed (the grid must not have
+ * changed since; RFA_ERR_STATE otherwise).  w_omega = dL/dOmega^N per voxel
+ * (float, [nx*ny*nz], memory space per inputs_on_device).  Outputs, each
+ * nullable: dL_dP[n_tines] (host, W^-1), dL_dctrl[m^3] (host; requires
+ * rfa_set_perfusion_bspline), dL_dperf[nx*ny*nz] = dL/df per voxel (float,
+ * memory space per inputs_on_device). */
+rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* dL_dctrl,
+                       float* dL_dperf);
+
+/* ---- Batched stepping of many grids (planning sweeps) ---------------------
+ * A batch advances n independent grids -- each with its own shape, spacing,
+ * tissue, needle and time step -- in lockstep: every step of every grid is
+ * one persistent kernel launch over the concatenated tile lists, and the
+ * whole step loop of an rfa_batch_step call is captured once in a hipGraph
+ * and replayed on later calls with the same step count.  The per-voxel
+ * arithmetic is that of rfa_step (Eq. (CUDAbioheat3d), Alg. 1 and 2), so a
+ * batch step leaves each grid bitwise in the state rfa_step would.
+ *
+ * The batch borrows the grids (it does not own them; destroy the batch
+ * before its grids).  Grids stay usable on their own: a grid stepped or
+ * modified outside the batch is picked up again at the next batch call. */
+typedef struct rfa_batch_s* rfa_batch;
+
+/* grids[n] must all have tissue; dt[n] seconds, each within its grid's
+ * stability bound (RFA_ERR_UNSTABLE otherwise). */
+rfa_status rfa_batch_create(int n, const rfa_grid* grids, const double* dt, rfa_batch* out);
+
+/* Advance every grid of the batch by n_steps of its own dt.  diags may be
+ * NULL or point to n rfa_diag (filled as rfa_step does for each grid; the
+ * call then synchronises). */
+rfa_status rfa_batch_step(rfa_batch b, int n_steps, rfa_diag* diags);
+
+/* Device time of the last rfa_batch_step's graph, milliseconds (HIP events
+ * on the batch's stream), and voxel-steps it advanced. */
+rfa_status rfa_batch_last_time(rfa_batch b, double* ms, long long* voxel_steps);
+
+void rfa_batch_destroy(rfa_batch b);
+
 void rfa_destroy_grid(rfa_grid g);
 const char* rfa_status_string(rfa_status s);
 const char* rfa_last_error(void);

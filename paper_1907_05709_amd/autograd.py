@@ -1,0 +1,58 @@
+"""torch.autograd bridge: damage integral as a function of tine powers and a
+B-spline perfusion-correction lattice.
+
+RfaFunction.apply(powers, ctrl, grid, n_steps, dt, ckpt_every) resets the
+grid, sets the powers (W, one per tine) and the perfusion multiplier
+f = exp(B ctrl), runs the checkpointed forward and returns Omega^N (the
+Arrhenius damage integral per voxel) as a tensor on the grid's device.
+backward() runs the library's discrete adjoint (recomputing each segment
+from its checkpoint) and returns dL/dpowers and dL/dctrl.  All computation
+is in librfa.so; this module only moves arguments.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import rfa
+
+
+class RfaFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, powers, ctrl, grid, n_steps: int, dt: float, ckpt_every: int):
+        if not grid.device:
+            raise ValueError("RfaFunction needs a device grid (device=True)")
+        grid.set_tine_powers(powers.detach().double().cpu().numpy())
+        grid.set_perfusion_bspline(ctrl.detach().float().cpu().numpy())
+        grid.reset_state()
+        grid.forward_checkpointed(int(n_steps), float(dt), int(ckpt_every))
+        _, omega, _ = grid.damage()
+        ctx.grid = grid
+        ctx.n_tines = int(powers.numel())
+        ctx.m = int(ctrl.shape[0])
+        ctx.pdev, ctx.pdtype = powers.device, powers.dtype
+        ctx.cdev, ctx.cdtype = ctrl.device, ctrl.dtype
+        return omega
+
+    @staticmethod
+    def backward(ctx, grad_omega):
+        dP, dc, _ = ctx.grid.adjoint(grad_omega.contiguous().float(), ctx.n_tines, ctx.m)
+        gP = torch.from_numpy(dP).to(ctx.pdev, ctx.pdtype)
+        gc = torch.from_numpy(dc).to(ctx.cdev, ctx.cdtype)
+        return gP, gc, None, None, None, None
+
+
+def coverage_loss(omega, labels, voxel_m3: float, tumour: int = 2, liver: int = 1,
+                  healthy_weight: float = 0.1):
+    """Soft undertreatment of the tumour plus healthy_weight x healthy-liver
+    damage volume in cm^3, with the damaged fraction d = sigmoid(4 ln Omega)
+    = Omega^4 / (1 + Omega^4).  omega, labels: tensors of the grid's shape."""
+    om = omega.double().clamp_min(0.0)
+    # sigmoid(4 ln Omega) written without the logarithm (Omega may be 0)
+    d = 1.0 / (1.0 + torch.where(om > 0, om, torch.ones_like(om)).pow(-4.0))
+    d = torch.where(om > 0, d, torch.zeros_like(d))
+    tum = labels == tumour
+    liv = labels == liver
+    u = (1.0 - d[tum]).mean() if bool(tum.any()) else d.sum() * 0.0
+    dv = d[liv].sum() * (voxel_m3 * 1e6)
+    return u + healthy_weight * dv

@@ -1,0 +1,37 @@
+// rfa_adjoint.h -- launchers of the adjoint and perfusion-field kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "rfa_kernels.h"
+
+namespace rfa {
+
+struct AdjointBuffers {
+  const float* lam_in;   // lambda^{n+1}
+  float* lam_out;        // lambda^n
+  const float* theta;    // theta^n (hi part of the recomputed state)
+  const uint8_t* lab;
+  const float* perf;     // perfusion multiplier, may be null
+  const float* w;        // dL/dOmega^N, zeroed where it cannot act
+  const Tables* tab;
+  float* sacc;           // += lambda^{n+1}          (dL/ds)
+  float* facc;           // += -B theta^n lambda^{n+1} (dL/df)
+};
+
+hipError_t launch_bspline_eval(Grid3 g, const float* ctrl, int m, float* f, hipStream_t st);
+// vfirst_a[s] = first voxel of knot span s along axis a, s = 0 .. m-3.
+hipError_t launch_bspline_grad(Grid3 g, const float* gf, const float* f, int m,
+                               const int* vfirst_x, const int* vfirst_y, const int* vfirst_z,
+                               double* gctrl, hipStream_t st);
+hipError_t launch_adjoint_weight(Grid3 g, const float* w, const float* om, const uint8_t* lab,
+                                 float cap, float* wa, hipStream_t st);
+hipError_t launch_adjoint_step(Grid3 g, const AdjointBuffers& a, const StepConst& K,
+                               hipStream_t st);
+// partial[t * nblk + b]: per-block sums of g_t(p) sacc_p dt / (rho c)_p.
+hipError_t launch_source_dot(Grid3 g, double dx, double dy, double dz, const uint8_t* lab,
+                             const Chord* chords, const int* tine_first, int n_tines,
+                             double sigma, const float* sacc, const ClassParams* cp_dev,
+                             double dt, double* partial, int nblk, hipStream_t st);
+
+}  // namespace rfa

@@ -17,6 +17,7 @@
 
 #include "../../include/rfa.h"
 #include "rfa_kernels.h"
+#include "rfa_adjoint.h"
 #include "rfa_step.h"
 
 using namespace rfa;
@@ -81,6 +82,27 @@ struct rfa_grid_s {
   std::vector<double> pts, power;
   double sigma = 0.0;
   double rf_power = 0.0;
+  Chord* chords_dev = nullptr;     // chords of the rasterised needle
+  int* first_dev = nullptr;        // first chord of each tine (+ end)
+  std::vector<double> tine_sums;   // integral of each tine's unnormalised density, m
+
+  // perfusion-correction B-spline (m^3 control points), if set
+  int bs_m = 0;
+  float* bs_ctrl = nullptr;
+  int* bs_vfirst = nullptr;        // [3][m - 2] first voxel of each knot span
+
+  // checkpointed forward and adjoint
+  int version = 0;                 // bumped by every change of inputs or state
+  bool adj_ready = false;
+  int adj_version = 0;
+  int adj_steps = 0, adj_every = 0, adj_nckpt = 0;
+  double adj_dt = 0.0;
+  float* ckpt = nullptr;           // [nckpt][2][N] hi, lo at segment starts
+  size_t ckpt_floats = 0;
+  float* traj = nullptr;           // [every + 1][N] recomputed hi
+  size_t traj_floats = 0;
+  float* adj_work = nullptr;       // lo ping-pong (2N), lambda (2N), sacc, facc, w, omega scratch
+  uint8_t* lab_scratch = nullptr;
 
   double dt_max = 0.0;
   long long steps = 0;
@@ -130,6 +152,14 @@ void free_all(rfa_grid g) {
   f(g->out4);
   f(g->counts);
   f(g->bad);
+  f(g->chords_dev);
+  f(g->first_dev);
+  f(g->bs_ctrl);
+  f(g->bs_vfirst);
+  f(g->ckpt);
+  f(g->traj);
+  f(g->adj_work);
+  f(g->lab_scratch);
   for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
   g->events.clear();
 }
@@ -214,6 +244,7 @@ rfa_status compute_dt_max(rfa_grid g) {
 // Rasterise the stored needle into q64 (zero if none) and invalidate s.
 rfa_status rasterise(rfa_grid g) {
   g->src_dt = -1.0;
+  ++g->version;
   if (!g->has_needle) {
     HIP_TRY(hipMemsetAsync(g->q64, 0, g->g.n() * sizeof(double), g->st));
     g->rf_power = 0.0;
@@ -295,8 +326,18 @@ rfa_status rasterise(rfa_grid g) {
                                  g->sigma, d_sums + nt, g->q64, g->st)) != hipSuccess) break;
     if ((e = hipStreamSynchronize(g->st)) != hipSuccess) break;
   } while (false);
-  cleanup();
-  if (e != hipSuccess) return fail(RFA_ERR_HIP, "source write failed: %s", hipGetErrorString(e));
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(RFA_ERR_HIP, "source write failed: %s", hipGetErrorString(e));
+  }
+  // keep the chord list and tine integrals for the adjoint's dL/dP
+  (void)hipFree(d_sums);
+  (void)hipFree(d_partial);
+  if (g->chords_dev) (void)hipFree(g->chords_dev);
+  if (g->first_dev) (void)hipFree(g->first_dev);
+  g->chords_dev = d_chords;
+  g->first_dev = d_first;
+  g->tine_sums = sums;
   double tot = 0.0;
   for (double p : g->power) tot += p;
   g->rf_power = tot;
@@ -312,11 +353,67 @@ rfa_status ensure_events(rfa_grid g, int count) {
   return RFA_OK;
 }
 
+// Per-dt coefficient tables and source increment of grid g.
+rfa_status prepare_dt(rfa_grid g, double dt) {
+  if (dt != g->tab_dt) {
+    build_tables(g, dt);
+    HIP_TRY(hipMemcpyAsync(g->tab_dev, &g->tab_host, sizeof(Tables), hipMemcpyHostToDevice, g->st));
+    HIP_TRY(hipStreamSynchronize(g->st));
+    g->tab_dt = dt;
+  }
+  if (dt != g->src_dt) {
+    HIP_TRY(launch_source_increment(g->g, g->lab, g->q64, g->cp_dev, dt, g->src, g->st));
+    g->src_dt = dt;
+  }
+  return RFA_OK;
+}
+
+rfa_status state_reduce(rfa_grid g, double out[4]);
+
+rfa_status ensure_energy(rfa_grid g) {
+  if (g->energy_valid) return RFA_OK;
+  double r[4];
+  rfa_status s = state_reduce(g, r);
+  if (s != RFA_OK) return s;
+  g->energy = r[0];
+  g->energy_valid = true;
+  return RFA_OK;
+}
+
+// Fill an rfa_diag from accumulated step partials acc[3] (perfusion J,
+// heat from held voxels J, cooling voxel count) and a fresh state reduction.
+rfa_status finish_diag(rfa_grid g, const double* acc, double e0, double dt, int n_steps,
+                       rfa_diag* diag);
+
 rfa_status state_reduce(rfa_grid g, double out[4]) {
   HIP_TRY(launch_state_reduce(g->g, g->lab, g->hi[g->cur], g->lo[g->cur], g->cp_dev,
                               g->dx * g->dy * g->dz, g->red, g->out4, g->st));
   HIP_TRY(hipMemcpyAsync(out, g->out4, 4 * sizeof(double), hipMemcpyDeviceToHost, g->st));
   HIP_TRY(hipStreamSynchronize(g->st));
+  return RFA_OK;
+}
+
+rfa_status finish_diag(rfa_grid g, const double* acc, double e0, double dt, int n_steps,
+                       rfa_diag* diag) {
+  double r[4];
+  rfa_status s = state_reduce(g, r);
+  if (s != RFA_OK) return s;
+  g->energy = r[0];
+  g->energy_valid = true;
+  const double vol = g->dx * g->dy * g->dz;
+  double met = 0.0;
+  for (int c = 0; c < g->n_classes; ++c)
+    met += g->table[c].q_met * (double)g->free_count[c] * vol;
+  diag->energy_J = r[0];
+  diag->injected_J = (g->rf_power + met) * dt * n_steps;
+  diag->perfusion_J = acc[0];
+  diag->boundary_J = acc[1];
+  diag->residual_J = (r[0] - e0) - (diag->injected_J - diag->perfusion_J + diag->boundary_J);
+  diag->mono_violations = (long long)std::llround(acc[2]);
+  diag->t_min_C = r[1];
+  diag->t_max_C = r[2];
+  diag->steps = n_steps;
+  if (r[3] > 0.0) return fail(RFA_ERR_NUMERIC, "%.0f non-finite voxels after step", r[3]);
   return RFA_OK;
 }
 
@@ -540,6 +637,8 @@ rfa_status rfa_set_perfusion(rfa_grid g, const float* factor) {
   if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
   if (!g->has_tissue) return fail(RFA_ERR_STATE, "set_tissue before set_perfusion");
   const size_t n = g->g.n();
+  ++g->version;
+  g->bs_m = 0;  // a plain multiplier replaces any B-spline field
   if (!factor) {
     if (g->perf) (void)hipFree(g->perf);
     g->perf = nullptr;
@@ -572,26 +671,12 @@ rfa_status rfa_step(rfa_grid g, int n_steps, double dt, rfa_diag* diag) {
   if (!finite_pos(dt)) return fail(RFA_ERR_ARG, "dt must be finite and positive");
   if (dt > g->dt_max)
     return fail(RFA_ERR_UNSTABLE, "dt %.6g s exceeds the stability bound %.6g s", dt, g->dt_max);
-  if (dt != g->tab_dt) {
-    build_tables(g, dt);
-    HIP_TRY(hipMemcpyAsync(g->tab_dev, &g->tab_host, sizeof(Tables), hipMemcpyHostToDevice, g->st));
-    HIP_TRY(hipStreamSynchronize(g->st));
-    g->tab_dt = dt;
-  }
-  if (dt != g->src_dt) {
-    HIP_TRY(launch_source_increment(g->g, g->lab, g->q64, g->cp_dev, dt, g->src, g->st));
-    g->src_dt = dt;
-  }
+  rfa_status sp = prepare_dt(g, dt);
+  if (sp != RFA_OK) return sp;
   const StepConst K = step_const(g, dt);
   double e0 = 0.0;
   if (diag) {
-    if (!g->energy_valid) {
-      double r[4];
-      rfa_status s = state_reduce(g, r);
-      if (s != RFA_OK) return s;
-      g->energy = r[0];
-      g->energy_valid = true;
-    }
+    if ((sp = ensure_energy(g)) != RFA_OK) return sp;
     e0 = g->energy;
     HIP_TRY(hipMemsetAsync(g->dacc, 0, 4 * sizeof(double), g->st));
   }
@@ -623,29 +708,14 @@ rfa_status rfa_step(rfa_grid g, int n_steps, double dt, rfa_diag* diag) {
     done += batch;
     g->steps += batch;
   }
-  if (n_steps > 0) g->energy_valid = false;
+  if (n_steps > 0) {
+    g->energy_valid = false;
+    ++g->version;
+  }
   if (diag) {
     double acc[4] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(acc, g->dacc, 3 * sizeof(double), hipMemcpyDeviceToHost, g->st));
-    double r[4];
-    s = state_reduce(g, r);
-    if (s != RFA_OK) return s;
-    g->energy = r[0];
-    g->energy_valid = true;
-    const double vol = g->dx * g->dy * g->dz;
-    double met = 0.0;
-    for (int c = 0; c < g->n_classes; ++c)
-      met += g->table[c].q_met * (double)g->free_count[c] * vol;
-    diag->energy_J = r[0];
-    diag->injected_J = (g->rf_power + met) * dt * n_steps;
-    diag->perfusion_J = acc[0];
-    diag->boundary_J = acc[1];
-    diag->residual_J = (r[0] - e0) - (diag->injected_J - diag->perfusion_J + diag->boundary_J);
-    diag->mono_violations = (long long)std::llround(acc[2]);
-    diag->t_min_C = r[1];
-    diag->t_max_C = r[2];
-    diag->steps = n_steps;
-    if (r[3] > 0.0) return fail(RFA_ERR_NUMERIC, "%.0f non-finite voxels after step", r[3]);
+    return finish_diag(g, acc, e0, dt, n_steps, diag);
   }
   return RFA_OK;
 }
@@ -739,6 +809,7 @@ rfa_status rfa_set_temperature(rfa_grid g, const double* t_C) {
   if (tmp) (void)hipFree(tmp);
   if (e != hipSuccess) return fail(RFA_ERR_HIP, "set_temperature: %s", hipGetErrorString(e));
   g->energy_valid = false;
+  ++g->version;
   return RFA_OK;
 }
 
@@ -827,6 +898,7 @@ rfa_status rfa_load_state(rfa_grid g, const void* buf, size_t bytes) {
   HIP_TRY(hipStreamSynchronize(g->st));
   g->steps = h.steps;
   g->energy_valid = false;
+  ++g->version;
   return RFA_OK;
 }
 
@@ -953,24 +1025,556 @@ rfa_status rfa_copy_bandwidth(size_t bytes, int reps, double* gbps) {
   if ((s = dmalloc(&b, n4)) != RFA_OK) { (void)hipFree(a); return s; }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipSuccess;
-  float ms = 0.f;
-  do {
-    if ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1))) break;
-    if ((e = hipMemsetAsync(a, 0, n4 * sizeof(float4), nullptr))) break;
-    if ((e = launch_copy(a, b, n4, nullptr))) break;
-    if ((e = hipEventRecord(e0, nullptr))) break;
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(a, b, n4, nullptr);
-    if (e) break;
-    if ((e = hipEventRecord(e1, nullptr)) || (e = hipEventSynchronize(e1))) break;
-    e = hipEventElapsedTime(&ms, e0, e1);
-  } while (false);
+  float best_ms = 1e30f;
+  // two copy kernels (plain, non-temporal x4); the faster one is the ceiling
+  for (int variant = 0; variant < 2 && e == hipSuccess; ++variant) {
+    auto launch = [&]() {
+      return variant == 0 ? launch_copy(a, b, n4, nullptr) : launch_copy_nt(a, b, n4, nullptr);
+    };
+    float ms = 0.f;
+    do {
+      if (!e0 && ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1)))) break;
+      if ((e = hipMemsetAsync(a, 0, n4 * sizeof(float4), nullptr))) break;
+      if ((e = launch())) break;
+      if ((e = hipEventRecord(e0, nullptr))) break;
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+      if (e) break;
+      if ((e = hipEventRecord(e1, nullptr)) || (e = hipEventSynchronize(e1))) break;
+      e = hipEventElapsedTime(&ms, e0, e1);
+    } while (false);
+    if (e == hipSuccess) best_ms = std::min(best_ms, ms);
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(a);
   (void)hipFree(b);
   if (e != hipSuccess) return fail(RFA_ERR_HIP, "copy bandwidth: %s", hipGetErrorString(e));
-  *gbps = 2.0 * n4 * sizeof(float4) * reps / (ms * 1e-3) / 1e9;
+  *gbps = 2.0 * n4 * sizeof(float4) * reps / (best_ms * 1e-3) / 1e9;
   return RFA_OK;
+}
+
+// ---- differentiation ----------------------------------------------------------------
+rfa_status rfa_set_perfusion_bspline(rfa_grid g, int m, const float* ctrl) {
+  if (!g || !ctrl) return fail(RFA_ERR_ARG, "grid and ctrl are required");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "set_tissue before set_perfusion_bspline");
+  if (m < 4 || m > 64) return fail(RFA_ERR_ARG, "m must be in 4..64");
+  const size_t nc = (size_t)m * m * m;
+  for (size_t j = 0; j < nc; ++j)
+    if (!std::isfinite(ctrl[j]) || std::fabs(ctrl[j]) > 30.0f)
+      return fail(RFA_ERR_ARG, "control value %zu not finite or |c| > 30", j);
+  const int dims[3] = {g->g.nx, g->g.ny, g->g.nz};
+  std::vector<int> vfirst(3 * (size_t)(m - 2), 0);
+  for (int a = 0; a < 3; ++a) {
+    const int n = dims[a];
+    int* vf = &vfirst[(size_t)a * (m - 2)];
+    // first voxel of knot span s (same span rule as the device kernels)
+    for (int s = 0; s <= m - 3; ++s) vf[s] = n;
+    for (int i = n - 1; i >= 0; --i) {
+      const double u = n > 1 ? (double)i * (double)(m - 3) / (double)(n - 1) : 0.0;
+      int s = (int)std::floor(u);
+      s = std::min(std::max(s, 0), m - 4);
+      for (int t = 0; t <= s; ++t) vf[t] = std::min(vf[t], i);
+    }
+    vf[m - 3] = n;
+  }
+  rfa_status s;
+  if (g->bs_m != m) {
+    if (g->bs_ctrl) (void)hipFree(g->bs_ctrl);
+    if (g->bs_vfirst) (void)hipFree(g->bs_vfirst);
+    g->bs_ctrl = nullptr;
+    g->bs_vfirst = nullptr;
+    g->bs_m = 0;
+    if ((s = dmalloc(&g->bs_ctrl, nc)) != RFA_OK) return s;
+    if ((s = dmalloc(&g->bs_vfirst, vfirst.size())) != RFA_OK) return s;
+  }
+  if (!g->perf && (s = dmalloc(&g->perf, g->g.n())) != RFA_OK) return s;
+  HIP_TRY(hipMemcpyAsync(g->bs_ctrl, ctrl, nc * sizeof(float), hipMemcpyHostToDevice, g->st));
+  HIP_TRY(hipMemcpyAsync(g->bs_vfirst, vfirst.data(), vfirst.size() * sizeof(int),
+                         hipMemcpyHostToDevice, g->st));
+  HIP_TRY(launch_bspline_eval(g->g, g->bs_ctrl, m, g->perf, g->st));
+  HIP_TRY(hipStreamSynchronize(g->st));
+  g->bs_m = m;
+  ++g->version;
+  return compute_dt_max(g);
+}
+
+rfa_status rfa_reset_state(rfa_grid g) {
+  if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "no tissue");
+  g->cur = 0;
+  g->steps = 0;
+  g->energy_valid = false;
+  ++g->version;
+  HIP_TRY(launch_reset_state(g->g, g->lab, g->hi[0], g->lo[0], g->om, g->cp_dev,
+                             (float)(g->opt.t_death - 37.0), g->st));
+  return RFA_OK;
+}
+
+rfa_status rfa_set_tine_powers(rfa_grid g, const double* power) {
+  if (!g || !power) return fail(RFA_ERR_ARG, "grid and power are required");
+  if (!g->has_needle) return fail(RFA_ERR_STATE, "no needle");
+  const size_t nt = g->power.size();
+  for (size_t t = 0; t < nt; ++t)
+    if (!(power[t] >= 0.0) || !std::isfinite(power[t]))
+      return fail(RFA_ERR_ARG, "power of tine %zu must be finite and >= 0", t);
+  std::vector<double> old = g->power;
+  g->power.assign(power, power + nt);
+  rfa_status s = rasterise(g);
+  if (s != RFA_OK) {
+    std::string err = g_last_error;
+    g->power = old;
+    rasterise(g);
+    g_last_error = err;
+  }
+  return s;
+}
+
+rfa_status rfa_forward_checkpointed(rfa_grid g, int n_steps, double dt, int ckpt_every) {
+  if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "set_tissue before forward");
+  if (n_steps < 1 || ckpt_every < 1) return fail(RFA_ERR_ARG, "n_steps, ckpt_every >= 1");
+  if (!finite_pos(dt)) return fail(RFA_ERR_ARG, "dt must be finite and positive");
+  if (dt > g->dt_max)
+    return fail(RFA_ERR_UNSTABLE, "dt %.6g s exceeds the stability bound %.6g s", dt, g->dt_max);
+  rfa_status s = prepare_dt(g, dt);
+  if (s != RFA_OK) return s;
+  const size_t n = g->g.n();
+  const int every = std::min(ckpt_every, n_steps);
+  const int nck = (n_steps + every - 1) / every;
+  const size_t need = (size_t)nck * 2 * n;
+  if (g->ckpt_floats < need) {
+    if (g->ckpt) (void)hipFree(g->ckpt);
+    g->ckpt = nullptr;
+    g->ckpt_floats = 0;
+    if ((s = dmalloc(&g->ckpt, need)) != RFA_OK) return s;
+    g->ckpt_floats = need;
+  }
+  g->adj_ready = false;
+  const StepConst K = step_const(g, dt);
+  StepState ss{g->hi, g->lo, &g->cur, g->lab, g->src, g->om, g->perf, g->tab_dev,
+               g->n_classes};
+  for (int seg = 0; seg < nck; ++seg) {
+    float* c = g->ckpt + (size_t)seg * 2 * n;
+    HIP_TRY(hipMemcpyAsync(c, g->hi[g->cur], n * sizeof(float), hipMemcpyDeviceToDevice, g->st));
+    HIP_TRY(hipMemcpyAsync(c + n, g->lo[g->cur], n * sizeof(float), hipMemcpyDeviceToDevice,
+                           g->st));
+    const int k = std::min(every, n_steps - seg * every);
+    s = run_steps(g->g, g->plan, ss, K, k, nullptr, kPartialSlots, g->dacc, nullptr, 1, nullptr,
+                  g->st);
+    if (s != RFA_OK) return fail(s, "forward launch failed");
+    g->steps += k;
+  }
+  g->energy_valid = false;
+  ++g->version;
+  g->adj_ready = true;
+  g->adj_version = g->version;
+  g->adj_steps = n_steps;
+  g->adj_every = every;
+  g->adj_nckpt = nck;
+  g->adj_dt = dt;
+  return RFA_OK;
+}
+
+rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* dL_dctrl,
+                       float* dL_dperf) {
+  if (!g || !w_omega) return fail(RFA_ERR_ARG, "grid and w_omega are required");
+  if (!g->adj_ready || g->version != g->adj_version)
+    return fail(RFA_ERR_STATE, "no checkpointed forward for the current state");
+  if (dL_dctrl && !g->bs_m) return fail(RFA_ERR_STATE, "no B-spline perfusion field");
+  if (dL_dP && !g->has_needle) return fail(RFA_ERR_STATE, "no needle");
+  const size_t n = g->g.n();
+  const int every = g->adj_every;
+  rfa_status s;
+  const size_t tneed = (size_t)(every + 1) * n;
+  if (g->traj_floats < tneed) {
+    if (g->traj) (void)hipFree(g->traj);
+    g->traj = nullptr;
+    g->traj_floats = 0;
+    if ((s = dmalloc(&g->traj, tneed)) != RFA_OK) return s;
+    g->traj_floats = tneed;
+  }
+  if (!g->adj_work && (s = dmalloc(&g->adj_work, 8 * n)) != RFA_OK) return s;
+  if (!g->lab_scratch && (s = dmalloc(&g->lab_scratch, n)) != RFA_OK) return s;
+  float* lopp[2] = {g->adj_work, g->adj_work + n};
+  float* lam[2] = {g->adj_work + 2 * n, g->adj_work + 3 * n};
+  float* sacc = g->adj_work + 4 * n;
+  float* facc = g->adj_work + 5 * n;
+  float* wv = g->adj_work + 6 * n;
+  float* om_s = g->adj_work + 7 * n;
+  HIP_TRY(hipMemcpyAsync(wv, w_omega, n * sizeof(float), kind_in(g), g->st));
+  HIP_TRY(launch_adjoint_weight(g->g, wv, g->om, g->lab, (float)g->opt.omega_cap, wv, g->st));
+  HIP_TRY(hipMemsetAsync(g->adj_work + 2 * n, 0, 4 * n * sizeof(float), g->st));
+  HIP_TRY(hipMemcpyAsync(g->lab_scratch, g->lab, n, hipMemcpyDeviceToDevice, g->st));
+  if ((s = prepare_dt(g, g->adj_dt)) != RFA_OK) return s;
+  const StepConst K = step_const(g, g->adj_dt);
+  int lc = 0;
+  for (int seg = g->adj_nckpt - 1; seg >= 0; --seg) {
+    const int k = std::min(every, g->adj_steps - seg * every);
+    const float* c = g->ckpt + (size_t)seg * 2 * n;
+    HIP_TRY(hipMemcpyAsync(g->traj, c, n * sizeof(float), hipMemcpyDeviceToDevice, g->st));
+    HIP_TRY(hipMemcpyAsync(lopp[0], c + n, n * sizeof(float), hipMemcpyDeviceToDevice, g->st));
+    for (int t = 0; t < k; ++t) {  // recompute theta^t of the segment (bitwise as forward)
+      StepBuffers b;
+      b.hi_in = g->traj + (size_t)t * n;
+      b.lo_in = lopp[t & 1];
+      b.hi_out = g->traj + (size_t)(t + 1) * n;
+      b.lo_out = lopp[(t + 1) & 1];
+      b.lab = g->lab_scratch;
+      b.src = g->src;
+      b.omega = om_s;
+      b.perf = g->perf;
+      b.tab = g->tab_dev;
+      b.partials = nullptr;
+      b.n_classes = g->n_classes;
+      HIP_TRY(launch_plan(g->g, g->plan, b, K, g->st));
+    }
+    for (int t = k - 1; t >= 0; --t) {
+      AdjointBuffers a;
+      a.lam_in = lam[lc];
+      a.lam_out = lam[1 - lc];
+      a.theta = g->traj + (size_t)t * n;
+      a.lab = g->lab;
+      a.perf = g->perf;
+      a.w = wv;
+      a.tab = g->tab_dev;
+      a.sacc = sacc;
+      a.facc = facc;
+      HIP_TRY(launch_adjoint_step(g->g, a, K, g->st));
+      lc = 1 - lc;
+    }
+  }
+  if (dL_dP) {
+    const int nt = (int)g->power.size();
+    constexpr int kBlk = 512;
+    double* part = nullptr;
+    if ((s = dmalloc(&part, (size_t)nt * kBlk)) != RFA_OK) return s;
+    std::vector<double> host((size_t)nt * kBlk);
+    hipError_t e = launch_source_dot(g->g, g->dx, g->dy, g->dz, g->lab, g->chords_dev,
+                                     g->first_dev, nt, g->sigma, sacc, g->cp_dev, g->adj_dt,
+                                     part, kBlk, g->st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(host.data(), part, host.size() * sizeof(double), hipMemcpyDeviceToHost,
+                         g->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+    (void)hipFree(part);
+    if (e != hipSuccess) return fail(RFA_ERR_HIP, "adjoint dL/dP: %s", hipGetErrorString(e));
+    for (int t = 0; t < nt; ++t) {
+      double acc = 0.0;
+      for (int b = 0; b < kBlk; ++b) acc += host[(size_t)t * kBlk + b];
+      dL_dP[t] = acc / g->tine_sums[t];
+    }
+  }
+  if (dL_dperf)
+    HIP_TRY(hipMemcpyAsync(dL_dperf, facc, n * sizeof(float), kind_out(g), g->st));
+  if (dL_dctrl) {
+    const int m = g->bs_m;
+    const size_t nc = (size_t)m * m * m;
+    double* gc = nullptr;
+    if ((s = dmalloc(&gc, nc)) != RFA_OK) return s;
+    hipError_t e = launch_bspline_grad(g->g, facc, g->perf, m, g->bs_vfirst,
+                                       g->bs_vfirst + (m - 2), g->bs_vfirst + 2 * (m - 2), gc,
+                                       g->st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dL_dctrl, gc, nc * sizeof(double), hipMemcpyDeviceToHost, g->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->st);
+    (void)hipFree(gc);
+    if (e != hipSuccess) return fail(RFA_ERR_HIP, "adjoint dL/dctrl: %s", hipGetErrorString(e));
+  }
+  HIP_TRY(hipStreamSynchronize(g->st));
+  return RFA_OK;
+}
+
+// ---- batches ---------------------------------------------------------------------
+}  // extern "C"
+
+struct rfa_batch_s {
+  std::vector<rfa_grid> grids;
+  std::vector<double> dt;
+  std::vector<BatchInstance> inst;  // host copy of the descriptor table
+  std::vector<int> first;           // item range of each instance
+  BatchInstance* inst_dev = nullptr;
+  BatchItem* items_dev = nullptr;
+  int* first_dev = nullptr;
+  float* partials = nullptr;        // [kPartialSlots][n_items][3]
+  double* dacc = nullptr;           // [n][3]
+  int n_items = 0;
+  int ty = 8;
+  int n_wg = 0;
+  int parity = 0;
+  long long voxels = 0;
+  hipStream_t st = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double last_ms = 0.0;
+  long long last_vs = 0;
+  struct Cached {
+    int n_steps, parity, diag;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<Cached> graphs;
+};
+
+namespace {
+
+constexpr int kBatchChunk = 16;  // x planes per batch work item
+
+void batch_free_device(rfa_batch b) {
+  for (auto& c : b->graphs) {
+    (void)hipGraphExecDestroy(c.exec);
+    (void)hipGraphDestroy(c.graph);
+  }
+  b->graphs.clear();
+  auto f = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  f(b->inst_dev);
+  f(b->items_dev);
+  f(b->first_dev);
+  f(b->partials);
+  f(b->dacc);
+  b->inst_dev = nullptr;
+  b->items_dev = nullptr;
+  b->first_dev = nullptr;
+  b->partials = nullptr;
+  b->dacc = nullptr;
+}
+
+// (Re)build the device descriptor table and work list from the grids'
+// current state; resets the batch parity and drops cached graphs.
+rfa_status batch_build(rfa_batch b) {
+  batch_free_device(b);
+  const int n = (int)b->grids.size();
+  b->inst.assign(n, BatchInstance{});
+  b->first.assign(n + 1, 0);
+  std::vector<BatchItem> items;
+  b->voxels = 0;
+  for (int i = 0; i < n; ++i) {
+    rfa_grid g = b->grids[i];
+    rfa_status s = prepare_dt(g, b->dt[i]);
+    if (s != RFA_OK) return s;
+    HIP_TRY(hipStreamSynchronize(g->st));
+    BatchInstance& I = b->inst[i];
+    I.hi[0] = g->hi[g->cur];
+    I.hi[1] = g->hi[1 - g->cur];
+    I.lo[0] = g->lo[g->cur];
+    I.lo[1] = g->lo[1 - g->cur];
+    I.lab = g->lab;
+    I.src = g->src;
+    I.om = g->om;
+    I.perf = g->perf;
+    I.tab = g->tab_dev;
+    I.K = step_const(g, b->dt[i]);
+    I.n_classes = g->n_classes;
+    I.nx = g->g.nx;
+    I.ny = g->g.ny;
+    I.nz = g->g.nz;
+    I.xc = std::min(kBatchChunk, g->g.nx);
+    if (!tiled_fits(g->g, I.xc)) return fail(RFA_ERR_ARG, "grid %d too large for a batch", i);
+    const TiledShape sh = tiled_shape(g->g, b->ty, I.xc);
+    b->first[i] = (int)items.size();
+    for (int tx = 0; tx < sh.chunks_x; ++tx)
+      for (int ty = 0; ty < sh.tiles_y; ++ty)
+        for (int tz = 0; tz < sh.tiles_z; ++tz) items.push_back(BatchItem{i, tz, ty, tx});
+    b->voxels += (long long)g->g.n();
+  }
+  b->first[n] = (int)items.size();
+  b->n_items = (int)items.size();
+  rfa_status s;
+  if ((s = dmalloc(&b->inst_dev, n)) || (s = dmalloc(&b->items_dev, items.size())) ||
+      (s = dmalloc(&b->first_dev, n + 1)) ||
+      (s = dmalloc(&b->partials, (size_t)kPartialSlots * b->n_items * 3)) ||
+      (s = dmalloc(&b->dacc, 3 * (size_t)n)))
+    return s;
+  HIP_TRY(hipMemcpyAsync(b->inst_dev, b->inst.data(), n * sizeof(BatchInstance),
+                         hipMemcpyHostToDevice, b->st));
+  HIP_TRY(hipMemcpyAsync(b->items_dev, items.data(), items.size() * sizeof(BatchItem),
+                         hipMemcpyHostToDevice, b->st));
+  HIP_TRY(hipMemcpyAsync(b->first_dev, b->first.data(), (n + 1) * sizeof(int),
+                         hipMemcpyHostToDevice, b->st));
+  HIP_TRY(hipStreamSynchronize(b->st));
+  int cus = 0, per_cu = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->grids[0]->device));
+  HIP_TRY(batch_max_resident(b->ty, &per_cu));
+  b->n_wg = std::max(1, std::min(b->n_items, cus * std::max(per_cu, 1)));
+  b->parity = 0;
+  return RFA_OK;
+}
+
+// Whether the grids still match the descriptor table (nobody stepped or
+// re-tissued a grid outside the batch, no dt change).
+bool batch_in_sync(rfa_batch b) {
+  for (size_t i = 0; i < b->grids.size(); ++i) {
+    rfa_grid g = b->grids[i];
+    const BatchInstance& I = b->inst[i];
+    if (!g->has_tissue || I.hi[b->parity] != g->hi[g->cur] || I.lab != g->lab ||
+        I.src != g->src || I.om != g->om || I.perf != g->perf || I.tab != g->tab_dev ||
+        I.n_classes != g->n_classes || g->tab_dt != b->dt[i] || g->src_dt != b->dt[i])
+      return false;
+  }
+  return true;
+}
+
+rfa_status batch_graph(rfa_batch b, int n_steps, bool diag, hipGraphExec_t* out) {
+  for (auto& c : b->graphs)
+    if (c.n_steps == n_steps && c.parity == b->parity && c.diag == (int)diag) {
+      *out = c.exec;
+      return RFA_OK;
+    }
+  if (b->graphs.size() >= 4) {
+    (void)hipGraphExecDestroy(b->graphs.front().exec);
+    (void)hipGraphDestroy(b->graphs.front().graph);
+    b->graphs.erase(b->graphs.begin());
+  }
+  HIP_TRY(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  int pending = 0;
+  for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
+    float* part = diag ? b->partials + (size_t)pending * b->n_items * 3 : nullptr;
+    e = launch_step_batch(b->ty, b->inst_dev, b->items_dev, b->n_items, b->n_wg,
+                          (b->parity + s) & 1, part, b->st);
+    if (e == hipSuccess && diag && ++pending == kPartialSlots) {
+      e = launch_reduce_batch(b->partials, pending, b->n_items, b->first_dev,
+                              (int)b->grids.size(), b->dacc, b->st);
+      pending = 0;
+    }
+  }
+  if (e == hipSuccess && diag && pending > 0)
+    e = launch_reduce_batch(b->partials, pending, b->n_items, b->first_dev,
+                            (int)b->grids.size(), b->dacc, b->st);
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(b->st, &graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(RFA_ERR_HIP, "batch graph capture failed: %s",
+                hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(RFA_ERR_HIP, "batch graph instantiate failed: %s", hipGetErrorString(e));
+  }
+  b->graphs.push_back(rfa_batch_s::Cached{n_steps, b->parity, (int)diag, graph, exec});
+  *out = exec;
+  return RFA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rfa_status rfa_batch_create(int n, const rfa_grid* grids, const double* dt, rfa_batch* out) {
+  if (!out) return fail(RFA_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || !grids || !dt) return fail(RFA_ERR_ARG, "n >= 1 grids and dt required");
+  for (int i = 0; i < n; ++i) {
+    if (!grids[i] || !grids[i]->has_tissue)
+      return fail(RFA_ERR_STATE, "grid %d has no tissue", i);
+    if (!finite_pos(dt[i])) return fail(RFA_ERR_ARG, "dt[%d] must be finite and positive", i);
+    if (dt[i] > grids[i]->dt_max)
+      return fail(RFA_ERR_UNSTABLE, "dt[%d] = %.6g s exceeds the stability bound %.6g s", i,
+                  dt[i], grids[i]->dt_max);
+    if (grids[i]->device != grids[0]->device)
+      return fail(RFA_ERR_ARG, "all grids of a batch must be on one device");
+    for (int j = 0; j < i; ++j)
+      if (grids[j] == grids[i]) return fail(RFA_ERR_ARG, "grid %d appears twice", i);
+  }
+  rfa_batch b = new (std::nothrow) rfa_batch_s();
+  if (!b) return fail(RFA_ERR_OOM, "host allocation failed");
+  b->grids.assign(grids, grids + n);
+  b->dt.assign(dt, dt + n);
+  hipError_t e = hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+  if (e != hipSuccess) {
+    rfa_batch_destroy(b);
+    return fail(RFA_ERR_HIP, "batch stream: %s", hipGetErrorString(e));
+  }
+  rfa_status s = batch_build(b);
+  if (s != RFA_OK) {
+    std::string err = g_last_error;
+    rfa_batch_destroy(b);
+    g_last_error = err;
+    return s;
+  }
+  *out = b;
+  return RFA_OK;
+}
+
+rfa_status rfa_batch_step(rfa_batch b, int n_steps, rfa_diag* diags) {
+  if (!b) return fail(RFA_ERR_ARG, "batch is NULL");
+  if (n_steps < 0) return fail(RFA_ERR_ARG, "n_steps must be >= 0");
+  if (n_steps == 0) return RFA_OK;
+  const int n = (int)b->grids.size();
+  for (int i = 0; i < n; ++i) {
+    rfa_grid g = b->grids[i];
+    if (!g->has_tissue) return fail(RFA_ERR_STATE, "grid %d lost its tissue", i);
+    if (b->dt[i] > g->dt_max)
+      return fail(RFA_ERR_UNSTABLE, "dt[%d] exceeds the grid's stability bound", i);
+    HIP_TRY(hipStreamSynchronize(g->st));
+  }
+  rfa_status s;
+  if (!batch_in_sync(b) && (s = batch_build(b)) != RFA_OK) return s;
+  std::vector<double> e0(n, 0.0);
+  if (diags) {
+    for (int i = 0; i < n; ++i) {
+      if ((s = ensure_energy(b->grids[i])) != RFA_OK) return s;
+      e0[i] = b->grids[i]->energy;
+    }
+    HIP_TRY(hipMemsetAsync(b->dacc, 0, 3 * (size_t)n * sizeof(double), b->st));
+  }
+  hipGraphExec_t exec = nullptr;
+  if ((s = batch_graph(b, n_steps, diags != nullptr, &exec)) != RFA_OK) return s;
+  HIP_TRY(hipEventRecord(b->ev0, b->st));
+  HIP_TRY(hipGraphLaunch(exec, b->st));
+  HIP_TRY(hipEventRecord(b->ev1, b->st));
+  b->last_vs = b->voxels * n_steps;
+  b->last_ms = -1.0;
+  b->parity = (b->parity + n_steps) & 1;
+  for (int i = 0; i < n; ++i) {
+    rfa_grid g = b->grids[i];
+    // later work on the grid's own stream waits for the batch
+    HIP_TRY(hipStreamWaitEvent(g->st, b->ev1, 0));
+    if (n_steps & 1) g->cur = 1 - g->cur;
+    g->steps += n_steps;
+    g->energy_valid = false;
+    ++g->version;
+  }
+  if (diags) {
+    HIP_TRY(hipStreamSynchronize(b->st));
+    std::vector<double> acc(3 * (size_t)n);
+    HIP_TRY(hipMemcpy(acc.data(), b->dacc, acc.size() * sizeof(double), hipMemcpyDeviceToHost));
+    rfa_status worst = RFA_OK;
+    for (int i = 0; i < n; ++i) {
+      s = finish_diag(b->grids[i], &acc[3 * i], e0[i], b->dt[i], n_steps, &diags[i]);
+      if (s != RFA_OK) worst = s;
+    }
+    if (worst != RFA_OK) return worst;
+  }
+  return RFA_OK;
+}
+
+rfa_status rfa_batch_last_time(rfa_batch b, double* ms, long long* voxel_steps) {
+  if (!b) return fail(RFA_ERR_ARG, "batch is NULL");
+  if (b->last_ms < 0.0 && b->last_vs > 0) {
+    HIP_TRY(hipEventSynchronize(b->ev1));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, b->ev0, b->ev1));
+    b->last_ms = t;
+  }
+  if (ms) *ms = b->last_ms < 0.0 ? 0.0 : b->last_ms;
+  if (voxel_steps) *voxel_steps = b->last_vs;
+  return RFA_OK;
+}
+
+void rfa_batch_destroy(rfa_batch b) {
+  if (!b) return;
+  if (b->st) (void)hipStreamSynchronize(b->st);
+  batch_free_device(b);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  if (b->st) (void)hipStreamDestroy(b->st);
+  delete b;
 }
 
 void rfa_destroy_grid(rfa_grid g) {

@@ -33,6 +33,25 @@ struct Chord {
   int pad;
 };
 
+// Density of one chord (uniform unit line density smeared by an isotropic
+// Gaussian of standard deviation sigma) at point (x, y, z), 1/m^2.  Chords
+// farther than 9 sigma contribute below 1e-17 of the peak and are skipped.
+__device__ __forceinline__ double chord_density(const Chord& c, double x, double y, double z,
+                                                double sigma) {
+  const double rx = x - c.mx, ry = y - c.my, rz = z - c.mz;
+  const double s = rx * c.ux + ry * c.uy + rz * c.uz;
+  const double r2 = rx * rx + ry * ry + rz * rz;
+  double dp2 = r2 - s * s;
+  dp2 = dp2 < 0.0 ? 0.0 : dp2;
+  const double cut = 9.0 * sigma;
+  if (dp2 > cut * cut || fabs(s) > c.half + cut) return 0.0;
+  const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
+  const double radial = exp(-dp2 * inv2s2) * inv2s2 * (1.0 / M_PI);
+  const double w = 1.0 / (M_SQRT2 * sigma);
+  const double axial = 0.5 * (erf((c.half - s) * w) + erf((c.half + s) * w));
+  return radial * axial;
+}
+
 struct StepBuffers {
   const float* hi_in;
   const float* lo_in;
@@ -58,6 +77,11 @@ hipError_t launch_step_naive(Grid3 g, const StepBuffers& b, const StepConst& K,
 // accumulated): acc += {perf, bnd, mono}.
 hipError_t launch_reduce_partials(const float* partials, int n_slots, int nwg,
                                   double* acc, hipStream_t st);
+
+// Per-instance sums of batch partials [n_slots][n_items][3]: instance i
+// owns items [first[i], first[i+1]); acc[3 i + c] += its sum.
+hipError_t launch_reduce_batch(const float* partials, int n_slots, int n_items,
+                               const int* first, int n_inst, double* acc, hipStream_t st);
 
 // ---- setup ---------------------------------------------------------------
 // Build internal label bytes from class labels; counts labels >= n_classes.
@@ -94,6 +118,8 @@ hipError_t launch_damage(Grid3 g, const uint8_t* lab, const float* om, uint8_t* 
                          unsigned long long* counts, hipStream_t st);
 // Plain streaming copy b = a of n4 float4 (bandwidth ceiling probe).
 hipError_t launch_copy(const float4* a, float4* b, size_t n4, hipStream_t st);
+// The same with non-temporal hints and four float4 per thread per pass.
+hipError_t launch_copy_nt(const float4* a, float4* b, size_t n4, hipStream_t st);
 // Free voxels per class [16].
 hipError_t launch_free_counts(Grid3 g, const uint8_t* lab, unsigned long long* counts,
                               hipStream_t st);

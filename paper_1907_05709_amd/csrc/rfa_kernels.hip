@@ -185,6 +185,44 @@ hipError_t launch_reduce_partials(const float* partials, int n_slots, int nwg, d
   return hipGetLastError();
 }
 
+// Batched diagnostics: block i sums, in fixed order, the partials of
+// instance i's items over n_slots steps into acc[3 i .. 3 i + 2].
+__global__ __launch_bounds__(256) void k_reduce_batch(const float* partials, int n_slots,
+                                                      int n_items, const int* first,
+                                                      double* acc) {
+  __shared__ double sh[3][4];
+  const int i = blockIdx.x;
+  const int a = first[i], cnt = first[i + 1] - first[i];
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int e = threadIdx.x; e < n_slots * cnt; e += 256) {
+    const int s = e / cnt, k = e - s * cnt;
+    const float* p = partials + ((size_t)s * n_items + a + k) * 3;
+    v0 += (double)p[0];
+    v1 += (double)p[1];
+    v2 += (double)p[2];
+  }
+  v0 = wave_sum_d(v0);
+  v1 = wave_sum_d(v1);
+  v2 = wave_sum_d(v2);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][w] = v0;
+    sh[1][w] = v1;
+    sh[2][w] = v2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3)
+    acc[3 * i + threadIdx.x] += ((sh[threadIdx.x][0] + sh[threadIdx.x][1]) +
+                                 (sh[threadIdx.x][2] + sh[threadIdx.x][3]));
+}
+
+hipError_t launch_reduce_batch(const float* partials, int n_slots, int n_items,
+                               const int* first, int n_inst, double* acc, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_batch, dim3(n_inst), dim3(256), 0, st, partials, n_slots,
+                     n_items, first, acc);
+  return hipGetLastError();
+}
+
 // ===========================================================================
 // Setup kernels
 // ===========================================================================
@@ -302,25 +340,6 @@ hipError_t launch_dt_bound(Grid3 g, const uint8_t* lab, const float* perf,
 }
 
 // ---- RF source (FP64) --------------------------------------------------------
-// Density of one chord (uniform unit line density smeared by an isotropic
-// Gaussian) at point (x, y, z).  Chords farther than 9 sigma contribute
-// below 1e-17 of the peak and are skipped.
-__device__ __forceinline__ double chord_density(const Chord& c, double x, double y, double z,
-                                                double sigma) {
-  const double rx = x - c.mx, ry = y - c.my, rz = z - c.mz;
-  const double s = rx * c.ux + ry * c.uy + rz * c.uz;
-  const double r2 = rx * rx + ry * ry + rz * rz;
-  double dp2 = r2 - s * s;
-  dp2 = dp2 < 0.0 ? 0.0 : dp2;
-  const double cut = 9.0 * sigma;
-  if (dp2 > cut * cut || fabs(s) > c.half + cut) return 0.0;
-  const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
-  const double radial = exp(-dp2 * inv2s2) * inv2s2 * (1.0 / M_PI);
-  const double w = 1.0 / (M_SQRT2 * sigma);
-  const double axial = 0.5 * (erf((c.half - s) * w) + erf((c.half + s) * w));
-  return radial * axial;
-}
-
 __device__ __forceinline__ double tine_density(const Chord* chords, int first, int last, double x,
                                                double y, double z, double sigma) {
   double g = 0.0;
@@ -524,9 +543,37 @@ __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ a,
     b[i] = a[i];
 }
 
+// Streaming copy with non-temporal hints, four 16-byte vectors per thread
+// per pass.
+typedef float v4f __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy_nt(const float4* __restrict__ a4,
+                                                 float4* __restrict__ b4, size_t n4) {
+  const v4f* a = reinterpret_cast<const v4f*>(a4);
+  v4f* b = reinterpret_cast<v4f*>(b4);
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n4; i += 4 * stride) {
+    const v4f v0 = __builtin_nontemporal_load(a + i);
+    const v4f v1 = __builtin_nontemporal_load(a + i + stride);
+    const v4f v2 = __builtin_nontemporal_load(a + i + 2 * stride);
+    const v4f v3 = __builtin_nontemporal_load(a + i + 3 * stride);
+    __builtin_nontemporal_store(v0, b + i);
+    __builtin_nontemporal_store(v1, b + i + stride);
+    __builtin_nontemporal_store(v2, b + i + 2 * stride);
+    __builtin_nontemporal_store(v3, b + i + 3 * stride);
+  }
+  for (; i < n4; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(a + i), b + i);
+}
+
 hipError_t launch_copy(const float4* a, float4* b, size_t n4, hipStream_t st) {
   const size_t blocks = std::min<size_t>((n4 + 255) / 256, 256 * 64);
   hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, a, b, n4);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_nt(const float4* a, float4* b, size_t n4, hipStream_t st) {
+  const size_t blocks = std::min<size_t>((n4 + 1023) / 1024, 256 * 8);
+  hipLaunchKernelGGL(k_copy_nt, dim3((unsigned)blocks), dim3(256), 0, st, a, b, n4);
   return hipGetLastError();
 }
 

@@ -14,6 +14,37 @@ struct TiledShape {
   int nwg;       // work-groups per launch
 };
 
+// One grid of a batch: its arrays, per-dt tables and step constants, and
+// the x-chunk length of its tiles.  Image 0 is the current image at batch
+// parity 0; a step at parity p reads image p and writes image 1 - p.
+struct BatchInstance {
+  float* hi[2];
+  float* lo[2];
+  uint8_t* lab;
+  const float* src;
+  float* om;
+  const float* perf;
+  const Tables* tab;
+  StepConst K;
+  int n_classes;
+  int nx, ny, nz;
+  int xc;
+};
+
+// One work item of a batch step: tile (tz, ty) over x-chunk tx of an instance.
+struct BatchItem {
+  int inst, tz, ty, tx;
+};
+
+// One step of every instance of a batch: a persistent grid of n_wg
+// work-groups of 64*ty threads walks the item list.  partials (nullable)
+// receives 3 floats per item.
+hipError_t launch_step_batch(int ty, const BatchInstance* inst, const BatchItem* items,
+                             int n_items, int n_wg, int parity, float* partials,
+                             hipStream_t st);
+// Work-groups of the batch kernel that fit on one CU at once.
+hipError_t batch_max_resident(int ty, int* per_cu);
+
 TiledShape tiled_shape(Grid3 g, int ty, int xc);
 // Whether a chunk of xc planes fits the kernel's 32-bit plane offsets.
 bool tiled_fits(Grid3 g, int xc);

@@ -93,8 +93,7 @@ struct TileCtx {
   unsigned hoff;     // halo element offset (voxels) in a plane
 };
 
-template <bool PERF>
-__device__ __forceinline__ void load_plane(const TileCtx& c, int x, Plane& q) {
+__device__ __forceinline__ void load_plane(const TileCtx& c, int x, bool perf, Plane& q) {
   const int xo = min(x, c.nx - 1) - c.xb;   // uniform
   const int xf = min(x, c.x1 - 1) - c.xb;   // uniform
   const int so4 = xo * (int)c.psz * 4, so1 = xo * (int)c.psz;
@@ -104,49 +103,55 @@ __device__ __forceinline__ void load_plane(const TileCtx& c, int x, Plane& q) {
   q.b = ld_u8(c.r.lab, c.col, so1);
   q.s = ld_f32(c.r.src, c.col * 4, sf4);
   q.om = ld_f32(c.r.om, c.col * 4, sf4);
-  q.pf = PERF ? ld_f32(c.r.perf, c.col * 4, sf4) : 1.0f;
+  q.pf = perf ? ld_f32(c.r.perf, c.col * 4, sf4) : 1.0f;
   q.hh = ld_f32(c.r.hi_in, c.hoff * 4, sf4);
   q.hl = ld_f32(c.r.lo_in, c.hoff * 4, sf4);
   q.hb = ld_u8(c.r.lab, c.hoff, sf1);
 }
 
-}  // namespace
 
-template <int TY, bool PERF>
-__global__ __launch_bounds__(64 * TY) void k_step_tiled(StepBuffers b, StepConst K, int nx,
-                                                        int ny, int nz, int xc, int tiles_z,
-                                                        int tiles_y, int nwg) {
-  constexpr int W = 66;             // 64 lanes + z halo
-  constexpr int ROWS = TY + 2;      // TY rows + y halo
-  constexpr int CELLS = ROWS * W;   // plus one scratch cell for threads without halo
-  constexpr int NT = 64 * TY;
-  __shared__ float2 cf[3 * kMaxClasses * kMaxClasses];
-  __shared__ float4 cls[kMaxClasses];
-  __shared__ float2 ts[2][CELLS + 1];
-  __shared__ uint8_t bs[2][CELLS + 1];
-  __shared__ float red[3][TY];
 
+// LDS working set of one work-group.
+template <int TY>
+struct TileSmem {
+  static constexpr int W = 66;            // 64 lanes + z halo
+  static constexpr int ROWS = TY + 2;     // TY rows + y halo
+  static constexpr int CELLS = ROWS * W;  // plus one scratch cell for threads without halo
+  float2 cf[3 * kMaxClasses * kMaxClasses];
+  float4 cls[kMaxClasses];
+  float2 ts[2][CELLS + 1];
+  uint8_t bs[2][CELLS + 1];
+  float red[3][TY];
+};
+
+// Stage the coefficient tables of the classes in use into LDS.
+template <int TY>
+__device__ __forceinline__ void stage_tables(TileSmem<TY>& sm, const Tables* tab, int nc) {
+  const int per_axis = nc * nc;
+  const float2* src = &tab->cf[0][0];
+  for (int t = threadIdx.x; t < 3 * per_axis; t += 64 * TY) {
+    const int ax = t / per_axis, r = t - ax * per_axis;
+    const int a = r / nc, c = r - a * nc;
+    const int i = ax * kMaxClasses * kMaxClasses + a * kMaxClasses + c;
+    sm.cf[i] = src[i];
+  }
+  if ((int)threadIdx.x < nc) sm.cls[threadIdx.x] = tab->cls[threadIdx.x];
+}
+
+// March one tile (tz, ty) over the x-chunk [tx*xc, tx*xc + xc) of one grid.
+// Tables must be staged (a barrier inside the march orders them).  The
+// work-group's partial sums are written to partials[wg_slot * 3] if
+// partials is not null.
+template <int TY>
+__device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& b,
+                                           const StepConst& K, bool perf, int nx, int ny,
+                                           int nz, int xc, int tz, int ty, int tx,
+                                           float* partials, int wg_slot) {
+  constexpr int W = TileSmem<TY>::W;
+  constexpr int CELLS = TileSmem<TY>::CELLS;
   const int lane = threadIdx.x & 63;
   const int wy = threadIdx.x >> 6;
   const int tid = threadIdx.x;
-  {
-    // stage the coefficient tables of the classes in use
-    const int nc = b.n_classes;
-    const int per_axis = nc * nc;
-    const float2* src = &b.tab->cf[0][0];
-    for (int t = tid; t < 3 * per_axis; t += NT) {
-      const int ax = t / per_axis, r = t - ax * per_axis;
-      const int a = r / nc, c = r - a * nc;
-      const int i = ax * kMaxClasses * kMaxClasses + a * kMaxClasses + c;
-      cf[i] = src[i];
-    }
-    if (tid < nc) cls[tid] = b.tab->cls[tid];
-  }
-
-  const int wg = remap_xcd(blockIdx.x, nwg);
-  const int tz = wg % tiles_z;
-  const int ty = (wg / tiles_z) % tiles_y;
-  const int tx = wg / (tiles_z * tiles_y);
   const int z = tz * 64 + lane;
   const int y = ty * TY + wy;
   const int x0 = tx * xc;
@@ -166,7 +171,7 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled(StepBuffers b, StepConst
     c.r.lab = make_rsrc(b.lab + off, rest);
     c.r.src = make_rsrc(b.src + off, rest * 4);
     c.r.om = make_rsrc(b.omega + off, rest * 4);
-    c.r.perf = make_rsrc(PERF ? b.perf + off : b.src + off, rest * 4);
+    c.r.perf = make_rsrc(perf ? b.perf + off : b.src + off, rest * 4);
     c.r.hi_out = make_rsrc(b.hi_out + off, rest * 4);
     c.r.lo_out = make_rsrc(b.lo_out + off, rest * 4);
   }
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled(StepBuffers b, StepConst
   }
   Plane q[kSlots];
 #pragma unroll
-  for (int k = 0; k < kAhead; ++k) load_plane<PERF>(c, x0 + k, q[k]);
+  for (int k = 0; k < kAhead; ++k) load_plane(c, x0 + k, perf, q[k]);
 
   Partial acc{0.0f, 0.0f, 0u};
   const int me = (wy + 1) * W + lane + 1;  // own LDS cell
@@ -212,22 +217,23 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled(StepBuffers b, StepConst
     constexpr int BUF = decltype(BUF_)::value;
     constexpr int SN = (S + 1) % kSlots;       // plane x+1
     constexpr int SL = (S + kAhead) % kSlots;  // slot receiving plane x+kAhead
-    load_plane<PERF>(c, x + kAhead, q[SL]);
+    load_plane(c, x + kAhead, perf, q[SL]);
     const Plane& P = q[S];
-    ts[BUF][me] = make_float2(P.h, P.l);
-    bs[BUF][me] = (uint8_t)P.b;
-    ts[BUF][hcell] = make_float2(P.hh, P.hl);
-    bs[BUF][hcell] = (uint8_t)P.hb;
+    sm.ts[BUF][me] = make_float2(P.h, P.l);
+    sm.bs[BUF][me] = (uint8_t)P.b;
+    sm.ts[BUF][hcell] = make_float2(P.hh, P.hl);
+    sm.bs[BUF][hcell] = (uint8_t)P.hb;
     __syncthreads();
-    const float2 ym = ts[BUF][me - W], yp = ts[BUF][me + W];
-    const float2 zm = ts[BUF][me - 1], zp = ts[BUF][me + 1];
-    const unsigned bym = bs[BUF][me - W], byp = bs[BUF][me + W];
-    const unsigned bzm = bs[BUF][me - 1], bzp = bs[BUF][me + 1];
+    const float2 ym = sm.ts[BUF][me - W], yp = sm.ts[BUF][me + W];
+    const float2 zm = sm.ts[BUF][me - 1], zp = sm.ts[BUF][me + 1];
+    const unsigned bym = sm.bs[BUF][me - W], byp = sm.bs[BUF][me + W];
+    const unsigned bzm = sm.bs[BUF][me - 1], bzp = sm.bs[BUF][me + 1];
     const Plane& N = q[SN];
     float nh, nl, om = P.om;
     unsigned nlab;
     voxel_step(P.h, P.l, P.b, hm, lm, bm, N.h, N.l, N.b, ym.x, ym.y, bym, yp.x, yp.y, byp,
-               zm.x, zm.y, bzm, zp.x, zp.y, bzp, P.s, P.pf, om, cf, cls, K, nh, nl, nlab, acc);
+               zm.x, zm.y, bzm, zp.x, zp.y, bzp, P.s, P.pf, om, sm.cf, sm.cls, K, nh, nl, nlab,
+               acc);
     if (inside) {
       const int so = (x - c.xb) * (int)c.psz;  // uniform
       st_f32(nh, c.r.hi_out, c.col * 4, so * 4);
@@ -253,28 +259,73 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled(StepBuffers b, StepConst
     if (x + 3 < c.x1) plane_step(I3{}, I1{}, x + 3);
   }
 
-  if (b.partials) {
+  if (partials) {
     const float pe = wave_sum(acc.perf);
     const float bn = wave_sum(acc.bnd);
     const unsigned mo = wave_sum_u(acc.mono);
     if (lane == 0) {
-      red[0][wy] = pe;
-      red[1][wy] = bn;
-      red[2][wy] = (float)mo;
+      sm.red[0][wy] = pe;
+      sm.red[1][wy] = bn;
+      sm.red[2][wy] = (float)mo;
     }
     __syncthreads();
     if (tid == 0) {
       float a0 = 0.f, a1 = 0.f, a2 = 0.f;
       for (int w = 0; w < TY; ++w) {
-        a0 += red[0][w];
-        a1 += red[1][w];
-        a2 += red[2][w];
+        a0 += sm.red[0][w];
+        a1 += sm.red[1][w];
+        a2 += sm.red[2][w];
       }
-      float* out = b.partials + (size_t)wg * 3;
+      float* out = partials + (size_t)wg_slot * 3;
       out[0] = a0;
       out[1] = a1;
       out[2] = a2;
     }
+  }
+}
+
+}  // namespace
+
+template <int TY, bool PERF>
+__global__ __launch_bounds__(64 * TY) void k_step_tiled(StepBuffers b, StepConst K, int nx,
+                                                        int ny, int nz, int xc, int tiles_z,
+                                                        int tiles_y, int nwg) {
+  __shared__ TileSmem<TY> sm;
+  stage_tables<TY>(sm, b.tab, b.n_classes);
+  const int wg = remap_xcd(blockIdx.x, nwg);
+  const int tz = wg % tiles_z;
+  const int ty = (wg / tiles_z) % tiles_y;
+  const int tx = wg / (tiles_z * tiles_y);
+  tile_march<TY>(sm, b, K, PERF, nx, ny, nz, xc, tz, ty, tx, b.partials, wg);
+}
+
+// Batched step: a persistent grid walks the work list of all instances
+// (items grouped by instance, taken round-robin), staging each item's
+// instance tables before its march.  parity selects the ping-pong image.
+template <int TY>
+__global__ __launch_bounds__(64 * TY) void k_step_batch(const BatchInstance* inst,
+                                                        const BatchItem* items, int n_items,
+                                                        int parity, float* partials) {
+  __shared__ TileSmem<TY> sm;
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const BatchItem w = items[it];
+    const BatchInstance& I = inst[w.inst];
+    StepBuffers b;
+    b.hi_in = I.hi[parity];
+    b.lo_in = I.lo[parity];
+    b.hi_out = I.hi[1 - parity];
+    b.lo_out = I.lo[1 - parity];
+    b.lab = I.lab;
+    b.src = I.src;
+    b.omega = I.om;
+    b.perf = I.perf;
+    b.tab = I.tab;
+    b.partials = nullptr;
+    b.n_classes = I.n_classes;
+    stage_tables<TY>(sm, I.tab, I.n_classes);
+    tile_march<TY>(sm, b, I.K, I.perf != nullptr, I.nx, I.ny, I.nz, I.xc, w.tz, w.ty, w.tx,
+                   partials, it);
+    __syncthreads();  // the next item restages the tables
   }
 }
 
@@ -305,6 +356,34 @@ static hipError_t launch_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
     hipLaunchKernelGGL((k_step_tiled<TY, false>), grid, block, 0, st, b, K, g.nx, g.ny, g.nz,
                        s.xc, s.tiles_z, s.tiles_y, s.nwg);
   return hipGetLastError();
+}
+
+hipError_t launch_step_batch(int ty, const BatchInstance* inst, const BatchItem* items,
+                             int n_items, int n_wg, int parity, float* partials,
+                             hipStream_t st) {
+  dim3 grid(n_wg), block(64 * ty);
+  switch (ty) {
+    case 4:
+      hipLaunchKernelGGL(k_step_batch<4>, grid, block, 0, st, inst, items, n_items, parity,
+                         partials);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_step_batch<8>, grid, block, 0, st, inst, items, n_items, parity,
+                         partials);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t batch_max_resident(int ty, int* per_cu) {
+  *per_cu = 0;
+  switch (ty) {
+    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_step_batch<4>, 256, 0);
+    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_step_batch<8>, 512, 0);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_step_tiled(const TiledShape& s, Grid3 g, const StepBuffers& b,

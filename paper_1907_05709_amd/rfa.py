@@ -82,6 +82,16 @@ _SIGS = {
     "rfa_get_plan": [C.c_void_p] + [C.POINTER(C.c_int)] * 5,
     "rfa_tune": [C.c_void_p, C.c_double, C.c_int],
     "rfa_copy_bandwidth": [C.c_size_t, C.c_int, C.POINTER(C.c_double)],
+    "rfa_set_perfusion_bspline": [C.c_void_p, C.c_int, C.c_void_p],
+    "rfa_reset_state": [C.c_void_p],
+    "rfa_set_tine_powers": [C.c_void_p, C.POINTER(C.c_double)],
+    "rfa_forward_checkpointed": [C.c_void_p, C.c_int, C.c_double, C.c_int],
+    "rfa_adjoint": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "rfa_batch_create": [C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_double),
+                         C.POINTER(C.c_void_p)],
+    "rfa_batch_step": [C.c_void_p, C.c_int, C.c_void_p],
+    "rfa_batch_last_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
+    "rfa_batch_destroy": [C.c_void_p],
     "rfa_destroy_grid": [C.c_void_p],
     "rfa_status_string": [C.c_int],
     "rfa_last_error": [],
@@ -110,6 +120,7 @@ def lib() -> C.CDLL:
             f.argtypes = args
             f.restype = C.c_int
         L.rfa_destroy_grid.restype = None
+        L.rfa_batch_destroy.restype = None
         L.rfa_status_string.restype = C.c_char_p
         L.rfa_last_error.restype = C.c_char_p
         _lib = L
@@ -259,6 +270,61 @@ def rfa_copy_bandwidth(nbytes: int, reps: int = 20) -> float:
     v = C.c_double()
     _check(lib().rfa_copy_bandwidth(int(nbytes), int(reps), C.byref(v)))
     return v.value
+
+
+def rfa_set_perfusion_bspline(g, ctrl: np.ndarray):
+    c = np.ascontiguousarray(ctrl, dtype=np.float32)
+    m = c.shape[0]
+    assert c.shape == (m, m, m)
+    _check(lib().rfa_set_perfusion_bspline(g, m, C.c_void_p(c.ctypes.data)))
+
+
+def rfa_reset_state(g):
+    _check(lib().rfa_reset_state(g))
+
+
+def rfa_set_tine_powers(g, power):
+    p = np.ascontiguousarray(power, dtype=np.float64)
+    _check(lib().rfa_set_tine_powers(g, p.ctypes.data_as(C.POINTER(C.c_double))))
+
+
+def rfa_forward_checkpointed(g, n_steps: int, dt: float, ckpt_every: int):
+    _check(lib().rfa_forward_checkpointed(g, int(n_steps), float(dt), int(ckpt_every)))
+
+
+def rfa_adjoint(g, w_ptr, dL_dP: Optional[np.ndarray], dL_dctrl: Optional[np.ndarray],
+                dperf_ptr):
+    """dL_dP, dL_dctrl: host float64 arrays filled in place (or None);
+    w_ptr / dperf_ptr: bulk pointers from _ptr()."""
+    _check(lib().rfa_adjoint(g, w_ptr,
+                             None if dL_dP is None else C.c_void_p(dL_dP.ctypes.data),
+                             None if dL_dctrl is None else C.c_void_p(dL_dctrl.ctypes.data),
+                             dperf_ptr))
+
+
+def rfa_batch_create(handles, dts) -> C.c_void_p:
+    n = len(handles)
+    arr = (C.c_void_p * n)(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    dt = (C.c_double * n)(*[float(d) for d in dts])
+    b = C.c_void_p()
+    _check(lib().rfa_batch_create(n, arr, dt, C.byref(b)))
+    return b
+
+
+def rfa_batch_step(b, n_steps: int, n_grids: int = 0, want_diag: bool = False):
+    diags = (rfa_diag * n_grids)() if want_diag else None
+    _check(lib().rfa_batch_step(b, int(n_steps), diags))
+    return [d.as_dict() for d in diags] if want_diag else None
+
+
+def rfa_batch_last_time(b):
+    ms, vs = C.c_double(), C.c_longlong()
+    _check(lib().rfa_batch_last_time(b, C.byref(ms), C.byref(vs)))
+    return ms.value, vs.value
+
+
+def rfa_batch_destroy(b):
+    lib().rfa_batch_destroy(b)
 
 
 def rfa_destroy_grid(g):
@@ -418,9 +484,66 @@ class Grid:
         """(kernel ms, launches, voxel-steps) since the last call."""
         return rfa_kernel_stats(self.h)
 
+    # -- differentiation
+    def set_perfusion_bspline(self, ctrl):
+        rfa_set_perfusion_bspline(self.h, ctrl)
+
+    def reset_state(self):
+        rfa_reset_state(self.h)
+
+    def set_tine_powers(self, power):
+        rfa_set_tine_powers(self.h, power)
+
+    def forward_checkpointed(self, n_steps: int, dt: float, ckpt_every: int):
+        rfa_forward_checkpointed(self.h, n_steps, dt, ckpt_every)
+
+    def adjoint(self, w_omega, n_tines: int = 0, m: int = 0, want_dperf: bool = False):
+        """Returns (dL/dP [n_tines] or None, dL/dctrl [m,m,m] or None,
+        dL/dperf per voxel or None) for dL/dOmega^N = w_omega."""
+        dP = np.zeros(n_tines) if n_tines else None
+        dc = np.zeros((m, m, m)) if m else None
+        dperf = self._alloc(np.float32) if want_dperf else None
+        if self.device:
+            w = w_omega.contiguous().float()
+            wp = _ptr(w, True, np.float32)
+        else:
+            w = np.ascontiguousarray(w_omega, dtype=np.float32)
+            wp = _ptr(w, False, np.float32)
+        rfa_adjoint(self.h, wp, dP, dc,
+                    None if dperf is None else _ptr(dperf, self.device, np.float32, True))
+        return dP, dc, dperf
+
     def plan(self) -> dict:
         return rfa_get_plan(self.h)
 
     def tune(self, dt: float, reps: int = 20) -> dict:
         rfa_tune(self.h, dt, reps)
         return self.plan()
+
+
+class Batch:
+    """Lockstep stepping of several Grid objects (each with its own dt) by
+    one persistent launch per step, the step loop replayed from a hipGraph.
+    The batch borrows the grids: close it before them."""
+
+    def __init__(self, grids, dts):
+        self.grids = list(grids)
+        self.h = rfa_batch_create([g.h for g in self.grids], dts)
+
+    def step(self, n_steps: int, diag: bool = False):
+        return rfa_batch_step(self.h, n_steps, len(self.grids), diag)
+
+    def last_time(self):
+        """(device ms of the last step call, voxel-steps it advanced)."""
+        return rfa_batch_last_time(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            rfa_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

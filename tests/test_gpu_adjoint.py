@@ -1,0 +1,165 @@
+"""Discrete adjoint on the GPU (checkpoint + recompute) against the FP64
+oracle's discrete adjoint and against central finite differences of the GPU
+forward; the autograd bridge against direct adjoint calls.
+
+Loss: soft undertreatment of the tumour + 0.1 x healthy-liver damage volume
+(cm^3), d = sigmoid(4 ln Omega).  Gradients with respect to the per-tine
+powers and a B-spline perfusion-correction lattice."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1907_05709_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+N_STEPS, DT, EVERY, M = 60, 0.2, 7, 8
+
+
+def coverage(case, omega):
+    """Loss and dL/dOmega in FP64 (numpy), same definition as the autograd
+    helper."""
+    lab = case.labels
+    om = np.clip(omega.astype(np.float64), 0.0, None)
+    om4 = om ** 4
+    d = om4 / (1.0 + om4)
+    tum = lab == W.LABEL_TUMOUR
+    liv = lab == W.LABEL_LIVER
+    V = np.prod(case.spacing) * 1e6
+    L = (1.0 - d[tum]).mean() + 0.1 * d[liv].sum() * V
+    dd = 4.0 * om ** 3 / (1.0 + om4) ** 2
+    w = np.zeros_like(om)
+    w[tum] = -dd[tum] / tum.sum()
+    w[liv] += 0.1 * V * dd[liv]
+    return L, w
+
+
+@pytest.fixture(scope="module")
+def setup():
+    O.build(force=False)
+    case = W.case_differentiation(n=32, dx=2e-3, n_steps=N_STEPS, dt=DT, seed=5001)
+    rng = np.random.default_rng(5)
+    ctrl = (0.3 * rng.standard_normal((M, M, M))).astype(np.float32)
+    return case, ctrl
+
+
+def gpu_grid(case, ctrl):
+    from paper_1907_05709_amd import rfa
+    g = rfa.Grid(case.shape, case.spacing)
+    g.load_case(case)
+    g.set_perfusion_bspline(ctrl)
+    return g
+
+
+def gpu_loss(g, case, powers):
+    g.set_tine_powers(powers)
+    g.reset_state()
+    g.forward_checkpointed(N_STEPS, DT, EVERY)
+    _, om, _ = g.damage()
+    return coverage(case, om)
+
+
+def test_adjoint_matches_oracle_discrete_adjoint(setup):
+    case, ctrl = setup
+    g = gpu_grid(case, ctrl)
+    P = case.needle.power.copy()
+    L, w = gpu_loss(g, case, P)
+    dP, dc, dperf = g.adjoint(w.astype(np.float32), len(P), M, want_dperf=True)
+    # oracle: same inputs, FP64 throughout
+    f = O.bspline_field(case.shape, ctrl.astype(np.float64))
+    q, gt, _ = O.source(case, per_tine=True)
+    dq, dperf_o = O.adjoint(case, w, n_steps=N_STEPS, dt=DT, q=q, perf=f)
+    dP_o = np.tensordot(gt, dq, axes=([1, 2, 3], [0, 1, 2]))
+    dc_o = O.bspline_grad(f, dperf_o, M)
+    print("dP gpu", dP, "\ndP oracle", dP_o)
+    assert np.abs(dP - dP_o).max() <= 1e-3 * np.abs(dP_o).max()
+    assert np.linalg.norm(dc - dc_o) <= 1e-3 * np.linalg.norm(dc_o)
+    big = np.abs(dperf_o) > 1e-3 * np.abs(dperf_o).max()
+    rel = np.abs(dperf[big] - dperf_o[big]) / np.abs(dperf_o[big])
+    assert np.median(rel) < 1e-4 and np.linalg.norm(dperf - dperf_o) <= 1e-3 * np.linalg.norm(dperf_o)
+    g.close()
+
+
+def test_adjoint_matches_central_differences(setup):
+    case, ctrl = setup
+    g = gpu_grid(case, ctrl)
+    P = case.needle.power.copy()
+    L0, w = gpu_loss(g, case, P)
+    dP, dc, _ = g.adjoint(w.astype(np.float32), len(P), M)
+    order = np.argsort(-np.abs(dP))
+    for k in order[:3]:
+        h = 1e-3 * P[k]
+        Pp, Pm = P.copy(), P.copy()
+        Pp[k] += h
+        Pm[k] -= h
+        fd = (gpu_loss(g, case, Pp)[0] - gpu_loss(g, case, Pm)[0]) / (2 * h)
+        print("tine", k, dP[k], fd)
+        assert abs(dP[k] - fd) <= 1e-3 * abs(fd) + 1e-6 * abs(L0) / P[k]
+    # control points: the two with the largest gradient
+    flat = np.argsort(-np.abs(dc).ravel())[:2]
+    for j in flat:
+        idx = np.unravel_index(j, dc.shape)
+        cp, cm = ctrl.copy(), ctrl.copy()
+        h = np.float32(1e-2)
+        cp[idx] += h
+        cm[idx] -= h
+        hh = float(cp[idx]) - float(cm[idx])
+        g.set_perfusion_bspline(cp)
+        Lp = gpu_loss(g, case, P)[0]
+        g.set_perfusion_bspline(cm)
+        Lm = gpu_loss(g, case, P)[0]
+        fd = (Lp - Lm) / hh
+        print("ctrl", idx, dc[idx], fd)
+        assert abs(dc[idx] - fd) <= 1e-2 * abs(fd)
+    g.close()
+
+
+def test_checkpoint_spacing_does_not_change_gradients(setup):
+    case, ctrl = setup
+    g = gpu_grid(case, ctrl)
+    P = case.needle.power.copy()
+    g.set_tine_powers(P)
+    out = []
+    for every in (EVERY, N_STEPS, 1):
+        g.reset_state()
+        g.forward_checkpointed(N_STEPS, DT, every)
+        _, om, _ = g.damage()
+        _, w = coverage(case, om)
+        out.append(g.adjoint(w.astype(np.float32), len(P), M, want_dperf=True))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+    for a, b in zip(out[0], out[2]):
+        assert np.array_equal(a, b)
+    g.close()
+
+
+def test_autograd_function_and_state_checks(setup):
+    import torch
+    from paper_1907_05709_amd import rfa
+    from paper_1907_05709_amd.autograd import RfaFunction, coverage_loss
+    case, ctrl = setup
+    g = rfa.Grid(case.shape, case.spacing, device=True)
+    g.load_case(case)
+    labels = torch.from_numpy(case.labels).cuda()
+    p = torch.tensor(case.needle.power, dtype=torch.float64, requires_grad=True)
+    c = torch.tensor(ctrl, dtype=torch.float32, requires_grad=True)
+    om = RfaFunction.apply(p, c, g, N_STEPS, DT, EVERY)
+    loss = coverage_loss(om, labels, float(np.prod(case.spacing)))
+    loss.backward()
+    # the same gradients through the direct calls
+    h = gpu_grid(case, ctrl)
+    L, w = gpu_loss(h, case, case.needle.power.copy())
+    dP, dc, _ = h.adjoint(w.astype(np.float32), len(case.needle.power), M)
+    assert abs(float(loss) - L) <= 1e-9 * abs(L)
+    assert np.allclose(p.grad.numpy(), dP, rtol=1e-5, atol=0)
+    assert np.allclose(c.grad.numpy(), dc, rtol=1e-4, atol=1e-6 * np.abs(dc).max())
+    # the grid changed since the forward: no adjoint
+    h.step(1, DT, diag=False)
+    with pytest.raises(rfa.RfaError) as e:
+        h.adjoint(w.astype(np.float32), len(case.needle.power), M)
+    assert e.value.status == rfa.RFA_ERR_STATE
+    torch.cuda.synchronize()
+    g.close()
+    h.close()

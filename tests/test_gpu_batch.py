@@ -1,0 +1,132 @@
+"""Batched stepping (one persistent launch per step over all grids, step
+loop replayed from a hipGraph) against independent single-grid runs and the
+FP64 oracle."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import parity
+from oracle import oracle as O
+from paper_1907_05709_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def small_sweep(n_inst=5, n_min=20, n_max=70, seed=4100):
+    cases = []
+    for i in range(n_inst):
+        c = W.case_planning_instance(i, n_min=n_min, n_max=n_max, base_seed=seed)
+        cases.append(c)
+    return cases
+
+
+def grid_for(case, **kw):
+    from paper_1907_05709_amd import rfa
+    g = rfa.Grid(case.shape, case.spacing, t_death=case.t_death, A=case.arrhenius_a,
+                 Ea=case.arrhenius_ea, R=case.gas_r, omega_cap=case.omega_cap, **kw)
+    g.load_case(case)
+    return g
+
+
+def state(g):
+    hi, lo = g.raw_state()
+    m, om, _ = g.damage()
+    return hi, lo, m, om
+
+
+def test_batch_bitwise_equals_single_grids_and_replays():
+    from paper_1907_05709_amd import rfa
+    cases = small_sweep()
+    assert len({c.shape for c in cases}) > 2          # uneven grids
+    singles = [grid_for(c) for c in cases]
+    batched = [grid_for(c) for c in cases]
+    b = rfa.Batch(batched, [c.dt for c in cases])
+    schedule = [37, 12, 37, 1]                        # odd counts, replayed graph
+    for n in schedule:
+        for g, c in zip(singles, cases):
+            g.step(n, c.dt, diag=False)
+        b.step(n)
+    ms, vs = b.last_time()
+    assert vs == sum(c.n_voxels for c in cases) and ms > 0
+    for g1, g2 in zip(singles, batched):
+        for a1, a2 in zip(state(g1), state(g2)):
+            assert np.array_equal(a1, a2)
+        assert g1.step_count() == g2.step_count() == sum(schedule)
+    b.close()
+    for g in singles + batched:
+        g.close()
+
+
+def test_batch_resyncs_after_a_grid_is_stepped_alone():
+    from paper_1907_05709_amd import rfa
+    cases = small_sweep(n_inst=3, seed=4200)
+    singles = [grid_for(c) for c in cases]
+    batched = [grid_for(c) for c in cases]
+    b = rfa.Batch(batched, [c.dt for c in cases])
+    b.step(10)
+    batched[1].step(3, cases[1].dt, diag=False)      # outside the batch
+    b.step(10)
+    for i, (g, c) in enumerate(zip(singles, cases)):
+        g.step(10, c.dt, diag=False)
+        if i == 1:
+            g.step(3, c.dt, diag=False)
+        g.step(10, c.dt, diag=False)
+    for g1, g2 in zip(singles, batched):
+        for a1, a2 in zip(state(g1), state(g2)):
+            assert np.array_equal(a1, a2)
+    b.close()
+    for g in singles + batched:
+        g.close()
+
+
+def test_batch_diagnostics_match_single_grids():
+    from paper_1907_05709_amd import rfa
+    cases = small_sweep(n_inst=4, seed=4300)
+    singles = [grid_for(c) for c in cases]
+    batched = [grid_for(c) for c in cases]
+    b = rfa.Batch(batched, [c.dt for c in cases])
+    d_b = b.step(70, diag=True)                       # crosses a reduction boundary
+    for g, c, db in zip(singles, cases, d_b):
+        ds = g.step(70, c.dt, diag=True)
+        assert ds["mono_violations"] == db["mono_violations"] == 0
+        assert ds["energy_J"] == db["energy_J"]
+        for k in ("perfusion_J", "boundary_J"):
+            assert math.isclose(ds[k], db[k], rel_tol=1e-5, abs_tol=1e-9)
+        scale = abs(db["injected_J"]) + abs(db["perfusion_J"]) + abs(db["boundary_J"])
+        assert abs(db["residual_J"]) <= 1e-5 * scale
+    b.close()
+    for g in singles + batched:
+        g.close()
+
+
+def test_batch_instance_matches_oracle():
+    from paper_1907_05709_amd import rfa
+    cases = small_sweep(n_inst=3, n_min=24, n_max=40, seed=4400)
+    grids = [grid_for(c) for c in cases]
+    b = rfa.Batch(grids, [c.dt for c in cases])
+    b.step(150)
+    for g, c in zip(grids, cases):
+        ost, _, _ = O.run(c, n_steps=150)
+        T = g.temperature()
+        mask, om, _ = g.damage()
+        parity.compare(c, T, mask, om, ost)
+    b.close()
+    for g in grids:
+        g.close()
+
+
+def test_batch_rejects_unstable_dt_and_bad_args():
+    from paper_1907_05709_amd import rfa
+    cases = small_sweep(n_inst=2, seed=4500)
+    grids = [grid_for(c) for c in cases]
+    with pytest.raises(rfa.RfaError) as e:
+        rfa.Batch(grids, [cases[0].dt, 10.0 * grids[1].dt_max()])
+    assert e.value.status == rfa.RFA_ERR_UNSTABLE
+    with pytest.raises(rfa.RfaError) as e:
+        rfa.Batch([grids[0], grids[0]], [cases[0].dt, cases[0].dt])
+    assert e.value.status == rfa.RFA_ERR_ARG
+    for g in grids:
+        g.close()
