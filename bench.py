@@ -118,6 +118,8 @@ def main():
     torch.cuda.set_device(0)
     if args.config == 4:
         return bench_batch(args)
+    if args.config == 5:
+        return bench_adjoint(args)
     case, name = workload(args.config)
     if args.time_steps > 0:
         case.n_steps = args.time_steps
@@ -249,6 +251,80 @@ def bench_batch(args):
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": None, "kernel": "k_step_batch",
                      "avg_launch_us": round(avg_launch_ms * 1e3, 3),
+                     "bytes_per_launch": bytes_per_launch},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args):
+    """Differentiation workload: 128^3 at 0.5 mm, 9-tine umbrella (60 W
+    shared by length), 600 steps of 0.02 s, checkpoint every 50 steps,
+    perfusion corrected by a 16^3 B-spline lattice (all zero).  One bench
+    step = reset, checkpointed forward, coverage loss and its gradient with
+    respect to the damage integral (torch, on the GPU), adjoint to the 9 tine
+    powers and the 4096 lattice values.  value = simulated voxel-steps per
+    second of forward + adjoint."""
+    import numpy as np
+    import torch
+    from paper_1907_05709_amd import rfa
+    from paper_1907_05709_amd import workloads as W
+    from paper_1907_05709_amd.autograd import coverage_loss
+
+    n_steps = args.time_steps if args.time_steps > 0 else 600
+    case = W.case_differentiation(n_steps=n_steps)
+    m, every = 16, 50
+    g = rfa.Grid(case.shape, case.spacing, device=True, time_kernels=TIME_PERIOD)
+    g.load_case(case)
+    g.set_perfusion_bspline(np.zeros((m, m, m), np.float32))
+    labels = torch.from_numpy(case.labels).cuda()
+    vox = float(np.prod(case.spacing))
+
+    def one_step():
+        g.reset_state()
+        g.forward_checkpointed(n_steps, case.dt, every)
+        _, om, _ = g.damage()
+        om.requires_grad_(True)
+        loss = coverage_loss(om, labels, vox)
+        (w,) = torch.autograd.grad(loss, om)
+        dP, dc, _ = g.adjoint(w.float(), case.needle.n_tines, m)
+        return float(loss), dP
+
+    for _ in range(args.warmup):
+        one_step()
+    g.kernel_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss, dP = one_step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, launches, _ = g.kernel_stats()
+    g.close()
+    value = case.n_voxels * n_steps * args.steps / wall / 1e9
+    avg_ms = kms / max(launches, 1)
+    bytes_per_launch = BYTES_PER_VOXEL_STEP * case.n_voxels
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GVoxel-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"differentiation: 9-tine umbrella 128^3 @0.5mm, {n_steps} x "
+                               f"{case.dt} s, checkpoint every {every}, 16^3 B-spline perfusion "
+                               f"lattice; value counts forward + adjoint per simulated step",
+                   "loss": loss, "dL_dP": [float(x) for x in dP]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "kernel": "k_step_tiled (forward and recompute)",
+                     "avg_launch_us": round(avg_ms * 1e3, 3),
                      "bytes_per_launch": bytes_per_launch},
     }
     print(json.dumps(out), flush=True)

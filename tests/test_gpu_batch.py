@@ -93,9 +93,11 @@ def test_batch_diagnostics_match_single_grids():
         ds = g.step(70, c.dt, diag=True)
         assert ds["mono_violations"] == db["mono_violations"] == 0
         assert ds["energy_J"] == db["energy_J"]
-        for k in ("perfusion_J", "boundary_J"):
-            assert math.isclose(ds[k], db[k], rel_tol=1e-5, abs_tol=1e-9)
+        # per-step sums are FP32 work-group partials in a different order:
+        # compare against the energy budget, not the (possibly ~0) value
         scale = abs(db["injected_J"]) + abs(db["perfusion_J"]) + abs(db["boundary_J"])
+        for k in ("perfusion_J", "boundary_J"):
+            assert abs(ds[k] - db[k]) <= 1e-6 * scale, (k, ds[k], db[k], scale)
         assert abs(db["residual_J"]) <= 1e-5 * scale
     b.close()
     for g in singles + batched:

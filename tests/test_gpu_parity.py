@@ -172,8 +172,10 @@ def test_tiled_kernel_bitwise_equals_reference(shape, ty, xc):
     assert plan["kernel"] == 2 and plan["tile_y"] == ty and plan["tile_x"] == min(xc, shape[0])
     assert np.array_equal(T1, T2) and np.array_equal(m1, m2) and np.array_equal(o1, o2)
     assert d1["mono_violations"] == d2["mono_violations"]
-    for k in ("perfusion_J", "boundary_J", "energy_J"):
-        assert math.isclose(d1[k], d2[k], rel_tol=1e-5, abs_tol=1e-9)
+    assert d1["energy_J"] == d2["energy_J"]
+    scale = abs(d1["injected_J"]) + abs(d1["perfusion_J"]) + abs(d1["boundary_J"])
+    for k in ("perfusion_J", "boundary_J"):
+        assert abs(d1[k] - d2[k]) <= 1e-6 * scale, (k, d1[k], d2[k], scale)
     g2.close()
 
 
