@@ -369,6 +369,42 @@ rfa_status prepare_dt(rfa_grid g, double dt) {
 }
 
 rfa_status state_reduce(rfa_grid g, double out[4]);
+rfa_status ensure_events(rfa_grid g, int count);
+
+// Advance the grid's current state n_steps with its launch plan (step
+// partials into g->dacc when diag), timing launch blocks with HIP events
+// when the grid was created with time_kernels.  Updates the step count.
+rfa_status timed_steps(rfa_grid g, const StepConst& K, int n_steps, bool diag) {
+  StepState ss{g->hi, g->lo, &g->cur, g->lab, g->src, g->om, g->perf, g->tab_dev,
+               g->n_classes};
+  rfa_status s = RFA_OK;
+  for (int done = 0; done < n_steps;) {
+    const int batch = std::min(n_steps - done, kTimedBatch);
+    hipEvent_t* ev = nullptr;
+    if (g->opt.time_kernels) {
+      if ((s = ensure_events(g, 2 * batch)) != RFA_OK) return s;
+      ev = g->events.data();
+    }
+    int timed = 0;
+    s = run_steps(g->g, g->plan, ss, K, batch, diag ? g->partials : nullptr, kPartialSlots,
+                  g->dacc, ev, g->opt.time_kernels, &timed, g->st);
+    if (s != RFA_OK)
+      return fail(s, "step launch failed: %s", hipGetErrorString(hipGetLastError()));
+    if (ev && timed > 0) {
+      HIP_TRY(hipEventSynchronize(ev[2 * timed - 1]));
+      for (int k = 0; k < timed; ++k) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+        g->kernel_ms += ms;
+      }
+      g->kernel_launches += batch;
+      g->kernel_voxel_steps += (long long)batch * g->plan.depth * (long long)g->g.n();
+    }
+    done += batch;
+    g->steps += batch;
+  }
+  return RFA_OK;
+}
 
 rfa_status ensure_energy(rfa_grid g) {
   if (g->energy_valid) return RFA_OK;
@@ -680,34 +716,8 @@ rfa_status rfa_step(rfa_grid g, int n_steps, double dt, rfa_diag* diag) {
     e0 = g->energy;
     HIP_TRY(hipMemsetAsync(g->dacc, 0, 4 * sizeof(double), g->st));
   }
-  StepState ss{g->hi, g->lo, &g->cur, g->lab, g->src, g->om, g->perf, g->tab_dev,
-               g->n_classes};
-  rfa_status s = RFA_OK;
-  for (int done = 0; done < n_steps;) {
-    const int batch = std::min(n_steps - done, kTimedBatch);
-    hipEvent_t* ev = nullptr;
-    if (g->opt.time_kernels) {
-      if ((s = ensure_events(g, 2 * batch)) != RFA_OK) return s;
-      ev = g->events.data();
-    }
-    int timed = 0;
-    s = run_steps(g->g, g->plan, ss, K, batch, diag ? g->partials : nullptr, kPartialSlots,
-                  g->dacc, ev, g->opt.time_kernels, &timed, g->st);
-    if (s != RFA_OK)
-      return fail(s, "step launch failed: %s", hipGetErrorString(hipGetLastError()));
-    if (ev && timed > 0) {
-      HIP_TRY(hipEventSynchronize(ev[2 * timed - 1]));
-      for (int k = 0; k < timed; ++k) {
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
-        g->kernel_ms += ms;
-      }
-      g->kernel_launches += batch;
-      g->kernel_voxel_steps += (long long)batch * g->plan.depth * (long long)g->g.n();
-    }
-    done += batch;
-    g->steps += batch;
-  }
+  rfa_status s = timed_steps(g, K, n_steps, diag != nullptr);
+  if (s != RFA_OK) return s;
   if (n_steps > 0) {
     g->energy_valid = false;
     ++g->version;
@@ -1151,18 +1161,13 @@ rfa_status rfa_forward_checkpointed(rfa_grid g, int n_steps, double dt, int ckpt
   }
   g->adj_ready = false;
   const StepConst K = step_const(g, dt);
-  StepState ss{g->hi, g->lo, &g->cur, g->lab, g->src, g->om, g->perf, g->tab_dev,
-               g->n_classes};
   for (int seg = 0; seg < nck; ++seg) {
     float* c = g->ckpt + (size_t)seg * 2 * n;
     HIP_TRY(hipMemcpyAsync(c, g->hi[g->cur], n * sizeof(float), hipMemcpyDeviceToDevice, g->st));
     HIP_TRY(hipMemcpyAsync(c + n, g->lo[g->cur], n * sizeof(float), hipMemcpyDeviceToDevice,
                            g->st));
     const int k = std::min(every, n_steps - seg * every);
-    s = run_steps(g->g, g->plan, ss, K, k, nullptr, kPartialSlots, g->dacc, nullptr, 1, nullptr,
-                  g->st);
-    if (s != RFA_OK) return fail(s, "forward launch failed");
-    g->steps += k;
+    if ((s = timed_steps(g, K, k, false)) != RFA_OK) return s;
   }
   g->energy_valid = false;
   ++g->version;
@@ -1299,7 +1304,10 @@ struct rfa_batch_s {
   double* dacc = nullptr;           // [n][3]
   int n_items = 0;
   int ty = 8;
+  int xc = 16;
   int n_wg = 0;
+  int req_wg = 0;                   // persistent work-groups (0: one per item)
+  int n_plain = 0;                  // items of grids without a perfusion field
   int parity = 0;
   long long voxels = 0;
   hipStream_t st = nullptr;
@@ -1316,7 +1324,6 @@ struct rfa_batch_s {
 
 namespace {
 
-constexpr int kBatchChunk = 16;  // x planes per batch work item
 
 void batch_free_device(rfa_batch b) {
   for (auto& c : b->graphs) {
@@ -1345,7 +1352,7 @@ rfa_status batch_build(rfa_batch b) {
   batch_free_device(b);
   const int n = (int)b->grids.size();
   b->inst.assign(n, BatchInstance{});
-  b->first.assign(n + 1, 0);
+  b->first.assign(2 * (size_t)n, 0);
   std::vector<BatchItem> items;
   b->voxels = 0;
   for (int i = 0; i < n; ++i) {
@@ -1368,20 +1375,30 @@ rfa_status batch_build(rfa_batch b) {
     I.nx = g->g.nx;
     I.ny = g->g.ny;
     I.nz = g->g.nz;
-    I.xc = std::min(kBatchChunk, g->g.nx);
+    I.xc = std::min(b->xc, g->g.nx);
     if (!tiled_fits(g->g, I.xc)) return fail(RFA_ERR_ARG, "grid %d too large for a batch", i);
-    const TiledShape sh = tiled_shape(g->g, b->ty, I.xc);
-    b->first[i] = (int)items.size();
-    for (int tx = 0; tx < sh.chunks_x; ++tx)
-      for (int ty = 0; ty < sh.tiles_y; ++ty)
-        for (int tz = 0; tz < sh.tiles_z; ++tz) items.push_back(BatchItem{i, tz, ty, tx});
     b->voxels += (long long)g->g.n();
   }
-  b->first[n] = (int)items.size();
+  // work items: grids without a perfusion field first, then those with one
+  // (two kernel variants); each grid's items are contiguous
+  b->n_plain = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i = 0; i < n; ++i) {
+      const BatchInstance& I = b->inst[i];
+      if ((I.perf != nullptr) != (pass == 1)) continue;
+      const TiledShape sh = tiled_shape(b->grids[i]->g, b->ty, I.xc);
+      b->first[2 * i] = (int)items.size();
+      for (int tx = 0; tx < sh.chunks_x; ++tx)
+        for (int ty = 0; ty < sh.tiles_y; ++ty)
+          for (int tz = 0; tz < sh.tiles_z; ++tz) items.push_back(BatchItem{i, tz, ty, tx});
+      b->first[2 * i + 1] = (int)items.size();
+    }
+    if (pass == 0) b->n_plain = (int)items.size();
+  }
   b->n_items = (int)items.size();
   rfa_status s;
   if ((s = dmalloc(&b->inst_dev, n)) || (s = dmalloc(&b->items_dev, items.size())) ||
-      (s = dmalloc(&b->first_dev, n + 1)) ||
+      (s = dmalloc(&b->first_dev, 2 * (size_t)n)) ||
       (s = dmalloc(&b->partials, (size_t)kPartialSlots * b->n_items * 3)) ||
       (s = dmalloc(&b->dacc, 3 * (size_t)n)))
     return s;
@@ -1389,13 +1406,11 @@ rfa_status batch_build(rfa_batch b) {
                          hipMemcpyHostToDevice, b->st));
   HIP_TRY(hipMemcpyAsync(b->items_dev, items.data(), items.size() * sizeof(BatchItem),
                          hipMemcpyHostToDevice, b->st));
-  HIP_TRY(hipMemcpyAsync(b->first_dev, b->first.data(), (n + 1) * sizeof(int),
+  HIP_TRY(hipMemcpyAsync(b->first_dev, b->first.data(), 2 * (size_t)n * sizeof(int),
                          hipMemcpyHostToDevice, b->st));
   HIP_TRY(hipStreamSynchronize(b->st));
-  int cus = 0, per_cu = 0;
-  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->grids[0]->device));
-  HIP_TRY(batch_max_resident(b->ty, &per_cu));
-  b->n_wg = std::max(1, std::min(b->n_items, cus * std::max(per_cu, 1)));
+  // persistent work-groups if requested, else one work-group per work item
+  b->n_wg = b->req_wg > 0 ? std::min(b->req_wg, b->n_items) : 0;
   b->parity = 0;
   return RFA_OK;
 }
@@ -1430,8 +1445,15 @@ rfa_status batch_graph(rfa_batch b, int n_steps, bool diag, hipGraphExec_t* out)
   int pending = 0;
   for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
     float* part = diag ? b->partials + (size_t)pending * b->n_items * 3 : nullptr;
-    e = launch_step_batch(b->ty, b->inst_dev, b->items_dev, b->n_items, b->n_wg,
-                          (b->parity + s) & 1, part, b->st);
+    const int par = (b->parity + s) & 1;
+    const int n_perf = b->n_items - b->n_plain;
+    const int wg_plain = b->n_wg > 0 ? std::min(b->n_wg, b->n_plain) : 0;
+    const int wg_perf = b->n_wg > 0 ? std::min(b->n_wg, n_perf) : 0;
+    e = launch_step_batch(b->ty, false, b->inst_dev, b->items_dev, 0, b->n_plain, wg_plain,
+                          par, part, b->st);
+    if (e == hipSuccess)
+      e = launch_step_batch(b->ty, true, b->inst_dev, b->items_dev, b->n_plain, n_perf,
+                            wg_perf, par, part, b->st);
     if (e == hipSuccess && diag && ++pending == kPartialSlots) {
       e = launch_reduce_batch(b->partials, pending, b->n_items, b->first_dev,
                               (int)b->grids.size(), b->dacc, b->st);
@@ -1550,6 +1572,31 @@ rfa_status rfa_batch_step(rfa_batch b, int n_steps, rfa_diag* diags) {
       if (s != RFA_OK) worst = s;
     }
     if (worst != RFA_OK) return worst;
+  }
+  return RFA_OK;
+}
+
+rfa_status rfa_batch_set_plan(rfa_batch b, int tile_y, int tile_x, int workgroups) {
+  if (!b) return fail(RFA_ERR_ARG, "batch is NULL");
+  if (tile_y != 0 && tile_y != 4 && tile_y != 8) return fail(RFA_ERR_ARG, "tile_y: 0, 4 or 8");
+  if (tile_x < 0 || workgroups < 0) return fail(RFA_ERR_ARG, "tile_x, workgroups >= 0");
+  if (b->st) HIP_TRY(hipStreamSynchronize(b->st));
+  if (tile_y) b->ty = tile_y;
+  if (tile_x) b->xc = tile_x;
+  b->req_wg = workgroups;
+  return batch_build(b);
+}
+
+rfa_status rfa_batch_get_plan(rfa_batch b, int* tile_y, int* tile_x, int* items,
+                              int* workgroups) {
+  if (!b) return fail(RFA_ERR_ARG, "batch is NULL");
+  if (tile_y) *tile_y = b->ty;
+  if (tile_x) *tile_x = b->xc;
+  if (items) *items = b->n_items;
+  if (workgroups) {
+    const int n_perf = b->n_items - b->n_plain;
+    *workgroups = b->n_wg > 0 ? std::min(b->n_wg, b->n_plain) + std::min(b->n_wg, n_perf)
+                              : b->n_items;
   }
   return RFA_OK;
 }

@@ -79,7 +79,7 @@ hipError_t launch_reduce_partials(const float* partials, int n_slots, int nwg,
                                   double* acc, hipStream_t st);
 
 // Per-instance sums of batch partials [n_slots][n_items][3]: instance i
-// owns items [first[i], first[i+1]); acc[3 i + c] += its sum.
+// owns items [first[2 i], first[2 i + 1]); acc[3 i + c] += its sum.
 hipError_t launch_reduce_batch(const float* partials, int n_slots, int n_items,
                                const int* first, int n_inst, double* acc, hipStream_t st);
 

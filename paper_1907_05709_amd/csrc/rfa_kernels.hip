@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const float* partials, int
                                                       double* acc) {
   __shared__ double sh[3][4];
   const int i = blockIdx.x;
-  const int a = first[i], cnt = first[i + 1] - first[i];
+  const int a = first[2 * i], cnt = first[2 * i + 1] - first[2 * i];
   double v0 = 0.0, v1 = 0.0, v2 = 0.0;
   for (int e = threadIdx.x; e < n_slots * cnt; e += 256) {
     const int s = e / cnt, k = e - s * cnt;

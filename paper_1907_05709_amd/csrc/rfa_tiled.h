@@ -36,14 +36,14 @@ struct BatchItem {
   int inst, tz, ty, tx;
 };
 
-// One step of every instance of a batch: a persistent grid of n_wg
-// work-groups of 64*ty threads walks the item list.  partials (nullable)
-// receives 3 floats per item.
-hipError_t launch_step_batch(int ty, const BatchInstance* inst, const BatchItem* items,
-                             int n_items, int n_wg, int parity, float* partials,
-                             hipStream_t st);
-// Work-groups of the batch kernel that fit on one CU at once.
-hipError_t batch_max_resident(int ty, int* per_cu);
+// One step of the items [first_item, first_item + n_items) of a batch, all
+// of instances with (perf) or without a perfusion field: n_wg > 0 persistent
+// work-groups of 64*ty threads walk the items, n_wg == 0 launches one
+// work-group per item.  partials (nullable) receives 3 floats per item,
+// indexed by item.
+hipError_t launch_step_batch(int ty, bool perf, const BatchInstance* inst,
+                             const BatchItem* items, int first_item, int n_items, int n_wg,
+                             int parity, float* partials, hipStream_t st);
 
 TiledShape tiled_shape(Grid3 g, int ty, int xc);
 // Whether a chunk of xc planes fits the kernel's 32-bit plane offsets.

@@ -299,34 +299,76 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled(StepBuffers b, StepConst
   tile_march<TY>(sm, b, K, PERF, nx, ny, nz, xc, tz, ty, tx, b.partials, wg);
 }
 
-// Batched step: a persistent grid walks the work list of all instances
-// (items grouped by instance, taken round-robin), staging each item's
-// instance tables before its march.  parity selects the ping-pong image.
-template <int TY>
+// Batched step over the work list of all instances (items grouped by
+// instance).  LOOP: a persistent grid walks the list round-robin; otherwise
+// one work-group per item, in XCD-aware order.  Each item stages its
+// instance's tables before its march.  parity selects the ping-pong image.
+template <int TY, bool PERF, bool LOOP>
 __global__ __launch_bounds__(64 * TY) void k_step_batch(const BatchInstance* inst,
-                                                        const BatchItem* items, int n_items,
-                                                        int parity, float* partials) {
+                                                        const BatchItem* items, int first_item,
+                                                        int n_items, int parity,
+                                                        float* partials) {
   __shared__ TileSmem<TY> sm;
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  // Work item and instance fields are the same for the whole work-group;
+  // say so (readfirstlane), so descriptors and constants live in scalar
+  // registers as in the single-grid kernel.
+  auto ui = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+  auto uf = [](float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+  };
+  auto up = [](auto* p) {
+    const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(v & 0xffffffffull));
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return reinterpret_cast<decltype(p)>(((unsigned long long)hi << 32) | lo);
+  };
+  auto one = [&](int it) {
     const BatchItem w = items[it];
-    const BatchInstance& I = inst[w.inst];
+    const BatchInstance& I = inst[ui(w.inst)];
     StepBuffers b;
-    b.hi_in = I.hi[parity];
-    b.lo_in = I.lo[parity];
-    b.hi_out = I.hi[1 - parity];
-    b.lo_out = I.lo[1 - parity];
-    b.lab = I.lab;
-    b.src = I.src;
-    b.omega = I.om;
-    b.perf = I.perf;
-    b.tab = I.tab;
+    b.hi_in = up(I.hi[parity]);
+    b.lo_in = up(I.lo[parity]);
+    b.hi_out = up(I.hi[1 - parity]);
+    b.lo_out = up(I.lo[1 - parity]);
+    b.lab = up(I.lab);
+    b.src = up(I.src);
+    b.omega = up(I.om);
+    b.perf = up(I.perf);
+    b.tab = up(I.tab);
     b.partials = nullptr;
-    b.n_classes = I.n_classes;
-    stage_tables<TY>(sm, I.tab, I.n_classes);
-    tile_march<TY>(sm, b, I.K, I.perf != nullptr, I.nx, I.ny, I.nz, I.xc, w.tz, w.ty, w.tx,
-                   partials, it);
-    __syncthreads();  // the next item restages the tables
+    b.n_classes = ui(I.n_classes);
+    StepConst K;
+    K.dtka = uf(I.K.dtka);
+    K.c2 = uf(I.K.c2);
+    K.tak = uf(I.K.tak);
+    K.clamp2 = uf(I.K.clamp2);
+    K.cap = uf(I.K.cap);
+    K.thr = uf(I.K.thr);
+    stage_tables<TY>(sm, b.tab, b.n_classes);
+    tile_march<TY>(sm, b, K, PERF, ui(I.nx), ui(I.ny), ui(I.nz), ui(I.xc), ui(w.tz), ui(w.ty),
+                   ui(w.tx), partials, it);
+  };
+  if (LOOP) {
+    for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
+      one(first_item + k);
+      __syncthreads();  // the next item restages the tables
+    }
+  } else {
+    one(first_item + remap_xcd(blockIdx.x, n_items));
   }
+}
+
+template <int TY, bool PERF>
+static hipError_t launch_batch_ty(const BatchInstance* inst, const BatchItem* items,
+                                  int first_item, int n_items, int n_wg, int parity,
+                                  float* partials, hipStream_t st) {
+  if (n_wg > 0)
+    hipLaunchKernelGGL((k_step_batch<TY, PERF, true>), dim3(n_wg), dim3(64 * TY), 0, st, inst,
+                       items, first_item, n_items, parity, partials);
+  else
+    hipLaunchKernelGGL((k_step_batch<TY, PERF, false>), dim3(n_items), dim3(64 * TY), 0, st,
+                       inst, items, first_item, n_items, parity, partials);
+  return hipGetLastError();
 }
 
 TiledShape tiled_shape(Grid3 g, int ty, int xc) {
@@ -358,32 +400,21 @@ static hipError_t launch_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
   return hipGetLastError();
 }
 
-hipError_t launch_step_batch(int ty, const BatchInstance* inst, const BatchItem* items,
-                             int n_items, int n_wg, int parity, float* partials,
-                             hipStream_t st) {
-  dim3 grid(n_wg), block(64 * ty);
-  switch (ty) {
-    case 4:
-      hipLaunchKernelGGL(k_step_batch<4>, grid, block, 0, st, inst, items, n_items, parity,
-                         partials);
-      break;
-    case 8:
-      hipLaunchKernelGGL(k_step_batch<8>, grid, block, 0, st, inst, items, n_items, parity,
-                         partials);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t batch_max_resident(int ty, int* per_cu) {
-  *per_cu = 0;
-  switch (ty) {
-    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_step_batch<4>, 256, 0);
-    case 8: return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_step_batch<8>, 512, 0);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_step_batch(int ty, bool perf, const BatchInstance* inst,
+                             const BatchItem* items, int first_item, int n_items, int n_wg,
+                             int parity, float* partials, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  if (ty == 4)
+    return perf ? launch_batch_ty<4, true>(inst, items, first_item, n_items, n_wg, parity,
+                                           partials, st)
+                : launch_batch_ty<4, false>(inst, items, first_item, n_items, n_wg, parity,
+                                            partials, st);
+  if (ty == 8)
+    return perf ? launch_batch_ty<8, true>(inst, items, first_item, n_items, n_wg, parity,
+                                           partials, st)
+                : launch_batch_ty<8, false>(inst, items, first_item, n_items, n_wg, parity,
+                                            partials, st);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_step_tiled(const TiledShape& s, Grid3 g, const StepBuffers& b,

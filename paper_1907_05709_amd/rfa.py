@@ -90,6 +90,8 @@ _SIGS = {
     "rfa_batch_create": [C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_double),
                          C.POINTER(C.c_void_p)],
     "rfa_batch_step": [C.c_void_p, C.c_int, C.c_void_p],
+    "rfa_batch_set_plan": [C.c_void_p, C.c_int, C.c_int, C.c_int],
+    "rfa_batch_get_plan": [C.c_void_p] + [C.POINTER(C.c_int)] * 4,
     "rfa_batch_last_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
     "rfa_batch_destroy": [C.c_void_p],
     "rfa_destroy_grid": [C.c_void_p],
@@ -317,6 +319,16 @@ def rfa_batch_step(b, n_steps: int, n_grids: int = 0, want_diag: bool = False):
     return [d.as_dict() for d in diags] if want_diag else None
 
 
+def rfa_batch_set_plan(b, tile_y: int = 0, tile_x: int = 0, workgroups: int = 0):
+    _check(lib().rfa_batch_set_plan(b, int(tile_y), int(tile_x), int(workgroups)))
+
+
+def rfa_batch_get_plan(b) -> dict:
+    v = [C.c_int() for _ in range(4)]
+    _check(lib().rfa_batch_get_plan(b, *[C.byref(x) for x in v]))
+    return dict(zip(("tile_y", "tile_x", "items", "workgroups"), [x.value for x in v]))
+
+
 def rfa_batch_last_time(b):
     ms, vs = C.c_double(), C.c_longlong()
     _check(lib().rfa_batch_last_time(b, C.byref(ms), C.byref(vs)))
@@ -536,6 +548,13 @@ class Batch:
     def last_time(self):
         """(device ms of the last step call, voxel-steps it advanced)."""
         return rfa_batch_last_time(self.h)
+
+    def set_plan(self, tile_y: int = 0, tile_x: int = 0, workgroups: int = 0):
+        rfa_batch_set_plan(self.h, tile_y, tile_x, workgroups)
+        return self.plan()
+
+    def plan(self) -> dict:
+        return rfa_batch_get_plan(self.h)
 
     def close(self):
         if getattr(self, "h", None):

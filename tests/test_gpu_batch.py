@@ -1,5 +1,5 @@
-"""Batched stepping (one persistent launch per step over all grids, step
-loop replayed from a hipGraph) against independent single-grid runs and the
+"""Batched stepping (one launch per step over all grids' tiles, step loop
+replayed from a hipGraph) against independent single-grid runs and the
 FP64 oracle."""
 from __future__ import annotations
 
@@ -55,6 +55,42 @@ def test_batch_bitwise_equals_single_grids_and_replays():
         for a1, a2 in zip(state(g1), state(g2)):
             assert np.array_equal(a1, a2)
         assert g1.step_count() == g2.step_count() == sum(schedule)
+    b.close()
+    for g in singles + batched:
+        g.close()
+
+
+@pytest.mark.parametrize("workgroups", [0, 7])
+def test_batch_mixed_perfusion_fields_and_persistent_plan(workgroups):
+    """Grids with a perfusion multiplier field run in their own launch; the
+    persistent schedule (few work-groups walking the item list) and the
+    one-work-group-per-item schedule give the same bits as single grids."""
+    from paper_1907_05709_amd import rfa
+    cases = small_sweep(n_inst=5, seed=4600)
+    rng = np.random.default_rng(4601)
+    fields = [None if i % 2 else rng.uniform(0.5, 2.0, c.shape).astype(np.float32)
+              for i, c in enumerate(cases)]
+    singles = [grid_for(c) for c in cases]
+    batched = [grid_for(c) for c in cases]
+    for g1, g2, f in zip(singles, batched, fields):
+        if f is not None:
+            g1.set_perfusion(f)
+            g2.set_perfusion(f)
+    dts = [0.9 * min(c.dt, g.dt_max()) for c, g in zip(cases, singles)]
+    b = rfa.Batch(batched, dts)
+    b.set_plan(0, 0, workgroups)
+    plan = b.plan()
+    if workgroups:
+        assert plan["workgroups"] <= 2 * workgroups
+    else:
+        assert plan["workgroups"] == plan["items"]
+    for n in (9, 4):
+        for g, dt in zip(singles, dts):
+            g.step(n, dt, diag=False)
+        b.step(n)
+    for g1, g2 in zip(singles, batched):
+        for a1, a2 in zip(state(g1), state(g2)):
+            assert np.array_equal(a1, a2)
     b.close()
     for g in singles + batched:
         g.close()
