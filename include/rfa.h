@@ -105,7 +105,11 @@ typedef struct {
   double omega_cap;   /* cap of the damage integral (1e30)                  */
   void* stream;       /* hipStream_t for all device work (NULL)            */
   int inputs_on_device; /* bulk voxel arrays are device pointers (0)        */
-  int depth;          /* steps per kernel launch; 0 = automatic (0)         */
+  int depth;          /* steps per kernel launch: 1, or 2 = temporal
+                         blocking (tiled kernel, tile_y 8 or 16; two steps
+                         per pass over memory, bitwise equal to two single
+                         steps; odd step counts end with a single step);
+                         0 = automatic (0)                                   */
   int kernel;         /* 0 automatic, 1 reference one-thread-per-voxel,
                          2 tiled 2.5-D (0)                                   */
   int tile_y;         /* tiled kernel: y rows per work-group (4, 8, 16);
@@ -199,9 +203,10 @@ rfa_status rfa_get_plan(rfa_grid g, int* kernel, int* depth, int* tile_y, int* t
                         int* workgroups);
 
 /* Time the candidate launch plans of this grid's shape on scratch copies of
- * its state (the state is not advanced) and keep the fastest.  dt as for
- * rfa_step; reps launches per candidate.  Results are cached per grid shape
- * for the process. */
+ * its state (the state is not advanced) and keep the fastest per step: the
+ * one-step tiled plans, and the two-step plans unless the grid was created
+ * with depth 1.  dt as for rfa_step; reps launches per candidate.  Results
+ * are cached per grid shape for the process. */
 rfa_status rfa_tune(rfa_grid g, double dt, int reps);
 
 /* Measured device-to-device streaming-copy bandwidth over `bytes` bytes

@@ -385,9 +385,9 @@ rfa_status timed_steps(rfa_grid g, const StepConst& K, int n_steps, bool diag) {
       if ((s = ensure_events(g, 2 * batch)) != RFA_OK) return s;
       ev = g->events.data();
     }
-    int timed = 0;
+    int timed = 0, launches = 0;
     s = run_steps(g->g, g->plan, ss, K, batch, diag ? g->partials : nullptr, kPartialSlots,
-                  g->dacc, ev, g->opt.time_kernels, &timed, g->st);
+                  g->dacc, ev, g->opt.time_kernels, &timed, &launches, g->st);
     if (s != RFA_OK)
       return fail(s, "step launch failed: %s", hipGetErrorString(hipGetLastError()));
     if (ev && timed > 0) {
@@ -397,8 +397,8 @@ rfa_status timed_steps(rfa_grid g, const StepConst& K, int n_steps, bool diag) {
         HIP_TRY(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
         g->kernel_ms += ms;
       }
-      g->kernel_launches += batch;
-      g->kernel_voxel_steps += (long long)batch * g->plan.depth * (long long)g->g.n();
+      g->kernel_launches += launches;
+      g->kernel_voxel_steps += (long long)launches * g->plan.depth * (long long)g->g.n();
     }
     done += batch;
     g->steps += batch;
@@ -495,7 +495,9 @@ rfa_status rfa_create_grid(int nx, int ny, int nz, double dx, double dy, double 
   if (!std::isfinite(o.t_death) || !(o.A >= 0.0) || !std::isfinite(o.A) || !finite_pos(o.Ea) ||
       !finite_pos(o.R) || !finite_pos(o.omega_cap) || o.omega_cap > 3.0e38)
     return fail(RFA_ERR_ARG, "invalid damage options");
-  if (o.depth < 0 || o.depth > kMaxDepth) return fail(RFA_ERR_ARG, "depth out of range");
+  if (o.depth < 0 || o.depth > kMaxDepth) return fail(RFA_ERR_ARG, "depth must be 0, 1 or 2");
+  if (o.depth == 2 && (o.kernel == kStepNaive || o.tile_y == 4))
+    return fail(RFA_ERR_ARG, "depth 2 needs the tiled kernel with tile_y 0, 8 or 16");
   if (o.kernel < 0 || o.kernel > 2) return fail(RFA_ERR_ARG, "kernel must be 0, 1 or 2");
   if (o.tile_y != 0 && o.tile_y != 4 && o.tile_y != 8 && o.tile_y != 16)
     return fail(RFA_ERR_ARG, "tile_y must be 0, 4, 8 or 16");
@@ -515,7 +517,7 @@ rfa_status rfa_create_grid(int nx, int ny, int nz, double dx, double dy, double 
     return fail(RFA_ERR_HIP, "no HIP device");
   }
   const size_t n = g->g.n();
-  g->plan = plan_default(g->g, o.kernel, o.tile_y, o.tile_x);
+  g->plan = plan_default(g->g, o.kernel, o.depth, o.tile_y, o.tile_x);
   const size_t nwg = (size_t)plan_max_wg(g->g);
   g->partial_floats = nwg * 3 * kPartialSlots;
   g->red_doubles = 4 * 1024 + 64;
@@ -943,9 +945,9 @@ rfa_status rfa_get_plan(rfa_grid g, int* kernel, int* depth, int* tile_y, int* t
 
 namespace {
 struct TuneKey {
-  int nx, ny, nz, perf;
+  int nx, ny, nz, perf, one_step;
   bool operator==(const TuneKey& o) const {
-    return nx == o.nx && ny == o.ny && nz == o.nz && perf == o.perf;
+    return nx == o.nx && ny == o.ny && nz == o.nz && perf == o.perf && one_step == o.one_step;
   }
 };
 std::vector<std::pair<TuneKey, StepPlan>> g_tuned;
@@ -957,7 +959,7 @@ rfa_status rfa_tune(rfa_grid g, double dt, int reps) {
   if (!finite_pos(dt) || reps < 1) return fail(RFA_ERR_ARG, "dt > 0 and reps >= 1 required");
   if (dt > g->dt_max)
     return fail(RFA_ERR_UNSTABLE, "dt %.6g s exceeds the stability bound %.6g s", dt, g->dt_max);
-  const TuneKey key{g->g.nx, g->g.ny, g->g.nz, g->perf ? 1 : 0};
+  const TuneKey key{g->g.nx, g->g.ny, g->g.nz, g->perf ? 1 : 0, g->opt.depth == 1 ? 1 : 0};
   for (auto& kv : g_tuned)
     if (kv.first == key) {
       g->plan = kv.second;
@@ -982,7 +984,7 @@ rfa_status rfa_tune(rfa_grid g, double dt, int reps) {
   if ((s = dmalloc(&lab2, n)) != RFA_OK) { (void)hipFree(om2); return s; }
   if ((s = ensure_events(g, 2)) != RFA_OK) { (void)hipFree(om2); (void)hipFree(lab2); return s; }
   StepPlan cand[32];
-  int nc = plan_candidates(g->g, cand, 32);
+  const int nc = plan_candidates(g->g, g->opt.depth == 1 ? 1 : kMaxDepth, cand, 32);
   const StepConst K = step_const(g, dt);
   StepBuffers b;
   b.hi_in = g->hi[g->cur];
@@ -1010,6 +1012,7 @@ rfa_status rfa_tune(rfa_grid g, double dt, int reps) {
     if ((e = hipEventSynchronize(g->events[1]))) break;
     float ms = 0.f;
     if ((e = hipEventElapsedTime(&ms, g->events[0], g->events[1]))) break;
+    ms /= (float)cand[c].depth;  // per step
     if (ms < best_ms) {
       best_ms = ms;
       best = cand[c];
@@ -1231,7 +1234,7 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
       b.tab = g->tab_dev;
       b.partials = nullptr;
       b.n_classes = g->n_classes;
-      HIP_TRY(launch_plan(g->g, g->plan, b, K, g->st));
+      HIP_TRY(launch_plan(g->g, plan_one(g->plan), b, K, g->st));
     }
     for (int t = k - 1; t >= 0; --t) {
       AdjointBuffers a;
@@ -1303,7 +1306,7 @@ struct rfa_batch_s {
   float* partials = nullptr;        // [kPartialSlots][n_items][3]
   double* dacc = nullptr;           // [n][3]
   int n_items = 0;
-  int ty = 8;
+  int ty = 4;
   int xc = 16;
   int n_wg = 0;
   int req_wg = 0;                   // persistent work-groups (0: one per item)

@@ -10,24 +10,31 @@
 
 namespace rfa {
 
-constexpr int kMaxDepth = 1;
+constexpr int kMaxDepth = 2;
 
 enum StepKind { kStepNaive = 1, kStepTiled = 2 };
 
 struct StepPlan {
   int kind;    // StepKind
-  int depth;   // steps per launch
+  int depth;   // steps per launch (1, or 2 with the tiled kernel)
   int ty;      // tile rows (y) per work-group (tiled)
   int xc;      // x planes per work-group (tiled)
   int nwg;     // work-groups per launch (stride of the partials)
+  // one-step plan for step counts not divisible by depth (equal to the
+  // plan itself when depth == 1)
+  int one_kind, one_ty, one_xc, one_nwg;
 };
 
 StepPlan plan_naive(Grid3 g);
 StepPlan plan_tiled(Grid3 g, int ty, int xc);
-// Heuristic plan from the options (kernel, tile_y, tile_x; 0 = automatic).
-StepPlan plan_default(Grid3 g, int kernel, int tile_y, int tile_x);
-// Candidate plans for tuning.
-int plan_candidates(Grid3 g, StepPlan* out, int max_out);
+StepPlan plan_tiled2(Grid3 g, int ty, int xc);
+// The one-step plan that accompanies a plan.
+StepPlan plan_one(const StepPlan& p);
+// Heuristic plan from the options (kernel, depth, tile_y, tile_x; 0 =
+// automatic).
+StepPlan plan_default(Grid3 g, int kernel, int depth, int tile_y, int tile_x);
+// Candidate plans for tuning (depth 1, and depth 2 if max_depth >= 2).
+int plan_candidates(Grid3 g, int max_depth, StepPlan* out, int max_out);
 // Largest partial stride any plan of this grid can need.
 int plan_max_wg(Grid3 g);
 
@@ -43,17 +50,20 @@ struct StepState {
   int n_classes;
 };
 
-// One launch of the plan reading image `in` and writing image `out`.
+// One launch of the plan (plan.depth steps) from b's input to its output image.
 hipError_t launch_plan(Grid3 g, const StepPlan& plan, const StepBuffers& b, const StepConst& K,
                        hipStream_t st);
 
-// Advance n_steps.  partials (nullable) has room for `slots` launches and is
-// folded into dacc[3] every `slots` launches and at the end.  If events is
-// not null, each block of `period` consecutive launches (the last one may be
-// shorter) is bracketed by the event pair events[2j], events[2j+1]
-// (j = 0, 1, ...; *n_timed receives the number of blocks).
+// Advance n_steps: n_steps / depth launches of the plan, then the rest with
+// its one-step plan.  partials (nullable) has room for `slots` launches and
+// is folded into dacc[3] every `slots` launches and at the end.  If events
+// is not null, each block of `period` consecutive launches of the plan (the
+// last one may be shorter) is bracketed by the event pair events[2j],
+// events[2j+1] (j = 0, 1, ...; *n_timed receives the number of blocks and
+// *n_launches the launches inside them); one-step launches are not timed.
 rfa_status run_steps(Grid3 g, const StepPlan& plan, StepState& s, const StepConst& K,
                      int n_steps, float* partials, int slots, double* dacc,
-                     hipEvent_t* events, int period, int* n_timed, hipStream_t st);
+                     hipEvent_t* events, int period, int* n_timed, int* n_launches,
+                     hipStream_t st);
 
 }  // namespace rfa

@@ -11,6 +11,22 @@ namespace {
 constexpr int kTargetWg = 1536;  // ~6 work-groups per CU on 256 CUs
 }
 
+namespace {
+StepPlan with_one(StepPlan p, const StepPlan& one) {
+  p.one_kind = one.kind;
+  p.one_ty = one.ty;
+  p.one_xc = one.xc;
+  p.one_nwg = one.nwg;
+  return p;
+}
+
+// x chunk giving about kTargetWg work-groups for `tiles` tiles per plane
+int default_xc(Grid3 g, int tiles) {
+  const int chunks = std::max(1, (kTargetWg + tiles - 1) / tiles);
+  return std::min(g.nx, std::max(4, (g.nx + chunks - 1) / chunks));
+}
+}  // namespace
+
 StepPlan plan_naive(Grid3 g) {
   StepPlan p;
   p.kind = kStepNaive;
@@ -18,7 +34,7 @@ StepPlan plan_naive(Grid3 g) {
   p.ty = 4;
   p.xc = 1;
   p.nwg = naive_wg_count(g);
-  return p;
+  return with_one(p, p);
 }
 
 StepPlan plan_tiled(Grid3 g, int ty, int xc) {
@@ -29,33 +45,64 @@ StepPlan plan_tiled(Grid3 g, int ty, int xc) {
   p.ty = ty;
   p.xc = xc;
   p.nwg = s.nwg;
-  return p;
+  return with_one(p, p);
 }
 
-StepPlan plan_default(Grid3 g, int kernel, int tile_y, int tile_x) {
+StepPlan plan_tiled2(Grid3 g, int ty, int xc) {
+  const TiledShape s = tiled2_shape(g, ty, xc);
+  StepPlan p;
+  p.kind = kStepTiled;
+  p.depth = 2;
+  p.ty = ty;
+  p.xc = xc;
+  p.nwg = s.nwg;
+  return with_one(p, plan_default(g, kStepTiled, 1, 0, 0));
+}
+
+StepPlan plan_one(const StepPlan& p) {
+  StepPlan o = p;
+  o.kind = p.one_kind;
+  o.depth = 1;
+  o.ty = p.one_ty;
+  o.xc = p.one_xc;
+  o.nwg = p.one_nwg;
+  return o;
+}
+
+StepPlan plan_default(Grid3 g, int kernel, int depth, int tile_y, int tile_x) {
   if (kernel == kStepNaive || !tiled_fits(g, 4)) return plan_naive(g);
+  if (depth == 2 && tiled2_fits(g, 4)) {
+    const int ty = tile_y == 16 ? 16 : 8;
+    const int tiles = ((g.nz + 61) / 62) * ((g.ny + ty - 3) / (ty - 2));
+    int xc = tile_x ? std::min(tile_x, g.nx) : default_xc(g, tiles);
+    while (xc > 4 && !tiled2_fits(g, xc)) xc /= 2;
+    return plan_tiled2(g, ty, xc);
+  }
   int ty = tile_y;
   if (ty == 0) ty = g.ny >= 64 ? 8 : 4;
-  int xc = tile_x;
-  if (xc == 0) {
-    const int tiles = ((g.nz + 63) / 64) * ((g.ny + ty - 1) / ty);
-    const int chunks = std::max(1, (kTargetWg + tiles - 1) / tiles);
-    xc = std::max(4, (g.nx + chunks - 1) / chunks);
-  }
-  xc = std::min(xc, g.nx);
+  const int tiles = ((g.nz + 63) / 64) * ((g.ny + ty - 1) / ty);
+  int xc = tile_x ? std::min(tile_x, g.nx) : default_xc(g, tiles);
   while (xc > 4 && !tiled_fits(g, xc)) xc /= 2;
   return plan_tiled(g, ty, xc);
 }
 
-int plan_candidates(Grid3 g, StepPlan* out, int max_out) {
+int plan_candidates(Grid3 g, int max_depth, StepPlan* out, int max_out) {
   int n = 0;
-  const int tys[] = {4, 8, 16};
   const int xcs[] = {4, 8, 16, 32, 64};
+  const int tys[] = {4, 8, 16};
   for (int ty : tys)
     for (int xc : xcs) {
       if (n >= max_out) return n;
       if ((xc > g.nx && xc != 4) || !tiled_fits(g, std::min(xc, g.nx))) continue;
       out[n++] = plan_tiled(g, ty, std::min(xc, g.nx));
+    }
+  if (max_depth < 2) return n;
+  const int tys2[] = {8, 16};
+  for (int ty : tys2)
+    for (int xc : xcs) {
+      if (n >= max_out) return n;
+      if ((xc > g.nx && xc != 4) || !tiled2_fits(g, std::min(xc, g.nx))) continue;
+      out[n++] = plan_tiled2(g, ty, std::min(xc, g.nx));
     }
   return n;
 }
@@ -64,21 +111,21 @@ int plan_max_wg(Grid3 g) {
   int m = naive_wg_count(g);
   const int tys[] = {4, 8, 16};
   for (int ty : tys) m = std::max(m, tiled_shape(g, ty, 1).nwg);
+  m = std::max(m, tiled2_shape(g, 8, 1).nwg);
   return m;
 }
 
 hipError_t launch_plan(Grid3 g, const StepPlan& plan, const StepBuffers& b, const StepConst& K,
                        hipStream_t st) {
   if (plan.kind == kStepNaive) return launch_step_naive(g, b, K, st);
+  if (plan.depth == 2) return launch_step_tiled2(tiled2_shape(g, plan.ty, plan.xc), g, b, K, st);
   return launch_step_tiled(tiled_shape(g, plan.ty, plan.xc), g, b, K, st);
 }
 
 rfa_status run_steps(Grid3 g, const StepPlan& plan, StepState& s, const StepConst& K,
                      int n_steps, float* partials, int slots, double* dacc, hipEvent_t* events,
-                     int period, int* n_timed, hipStream_t st) {
-  int pending = 0;
-  int timed = 0;
-  for (int n = 0; n < n_steps; ++n) {
+                     int period, int* n_timed, int* n_launches, hipStream_t st) {
+  auto buffers = [&]() {
     StepBuffers b;
     b.hi_in = s.hi[*s.cur];
     b.lo_in = s.lo[*s.cur];
@@ -90,11 +137,20 @@ rfa_status run_steps(Grid3 g, const StepPlan& plan, StepState& s, const StepCons
     b.perf = s.perf;
     b.tab = s.tab;
     b.n_classes = s.n_classes;
+    b.partials = nullptr;
+    return b;
+  };
+  const int n_main = n_steps / plan.depth;
+  const int n_rest = n_steps - n_main * plan.depth;
+  int pending = 0;
+  int timed = 0;
+  for (int n = 0; n < n_main; ++n) {
+    StepBuffers b = buffers();
     b.partials = partials ? partials + (size_t)pending * plan.nwg * 3 : nullptr;
     // Blocks of `period` consecutive launches are bracketed by one event pair
     // (the diagnostic reductions fall between blocks, never inside one).
     const bool open = events && (n % period) == 0;
-    const bool close = events && ((n % period) == period - 1 || n == n_steps - 1);
+    const bool close = events && ((n % period) == period - 1 || n == n_main - 1);
     if (open && hipEventRecord(events[2 * timed], st) != hipSuccess) return RFA_ERR_HIP;
     if (launch_plan(g, plan, b, K, st) != hipSuccess) return RFA_ERR_HIP;
     if (close) {
@@ -111,7 +167,17 @@ rfa_status run_steps(Grid3 g, const StepPlan& plan, StepState& s, const StepCons
   if (partials && pending > 0)
     if (launch_reduce_partials(partials, pending, plan.nwg, dacc, st) != hipSuccess)
       return RFA_ERR_HIP;
+  const StepPlan one = plan_one(plan);
+  for (int r = 0; r < n_rest; ++r) {
+    StepBuffers b = buffers();
+    b.partials = partials;
+    if (launch_plan(g, one, b, K, st) != hipSuccess) return RFA_ERR_HIP;
+    *s.cur = 1 - *s.cur;
+    if (partials && launch_reduce_partials(partials, 1, one.nwg, dacc, st) != hipSuccess)
+      return RFA_ERR_HIP;
+  }
   if (n_timed) *n_timed = timed;
+  if (n_launches) *n_launches = events ? n_main : 0;
   return RFA_OK;
 }
 

@@ -8,7 +8,7 @@
 namespace rfa {
 
 struct TiledShape {
-  int ty;        // waves (y rows) per work-group: 4, 8 or 16
+  int ty;        // waves (y rows of the footprint) per work-group: 4, 8 or 16
   int xc;        // x planes per work-group
   int tiles_z, tiles_y, chunks_x;
   int nwg;       // work-groups per launch
@@ -50,5 +50,13 @@ TiledShape tiled_shape(Grid3 g, int ty, int xc);
 bool tiled_fits(Grid3 g, int xc);
 hipError_t launch_step_tiled(const TiledShape& s, Grid3 g, const StepBuffers& b,
                              const StepConst& K, hipStream_t st);
+
+// Two steps per launch (temporal blocking, ty = 8 or 16): tiles own
+// 62 x (ty - 2) columns and recompute a one-voxel rim of the first step.
+// The partials receive the sums of both steps.
+TiledShape tiled2_shape(Grid3 g, int ty, int xc);
+bool tiled2_fits(Grid3 g, int xc);
+hipError_t launch_step_tiled2(const TiledShape& s, Grid3 g, const StepBuffers& b,
+                              const StepConst& K, hipStream_t st);
 
 }  // namespace rfa

@@ -31,27 +31,17 @@
 
 #include <type_traits>
 
+#include "rfa_tile_common.h"
 #include "rfa_tiled.h"
 
 namespace rfa {
 
 namespace {
 
+using namespace tile;
+
 constexpr int kAhead = 3;           // planes in flight ahead of the computed one
 constexpr int kSlots = kAhead + 1;  // register ring size
-constexpr int kRsrcWord3 = 0x00020000;  // gfx9 buffer descriptor word 3 (32-bit data format)
-
-__device__ __forceinline__ int remap_xcd(int wg, int nwg) {
-  // Hardware places work-group w on XCD w % 8.  Give XCD k the contiguous
-  // range of logical tiles [base_k, base_k + count_k).
-  constexpr int kXcd = 8;
-  const int per = nwg / kXcd;
-  const int rem = nwg % kXcd;
-  const int xcd = wg % kXcd;
-  const int slot = wg / kXcd;
-  const int base = xcd * per + (xcd < rem ? xcd : rem);
-  return base + slot;
-}
 
 // Registers of one plane for one thread.
 struct Plane {
@@ -66,23 +56,6 @@ struct Plane {
 struct Rsrc {
   __amdgpu_buffer_rsrc_t hi_in, lo_in, lab, src, om, perf, hi_out, lo_out;
 };
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, size_t bytes) {
-  const int n = bytes > 0x7fffffffu ? 0x7fffffff : (int)bytes;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, kRsrcWord3);
-}
-
-// 32-bit buffer loads/stores move raw bits: reinterpret, never convert.
-__device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
-}
-__device__ __forceinline__ void st_f32(float v, __amdgpu_buffer_rsrc_t r, unsigned voff,
-                                       int soff) {
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, soff, 0);
-}
-__device__ __forceinline__ unsigned ld_u8(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
-  return (unsigned)__builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, soff, 0);
-}
 
 struct TileCtx {
   Rsrc r;
@@ -123,20 +96,6 @@ struct TileSmem {
   uint8_t bs[2][CELLS + 1];
   float red[3][TY];
 };
-
-// Stage the coefficient tables of the classes in use into LDS.
-template <int TY>
-__device__ __forceinline__ void stage_tables(TileSmem<TY>& sm, const Tables* tab, int nc) {
-  const int per_axis = nc * nc;
-  const float2* src = &tab->cf[0][0];
-  for (int t = threadIdx.x; t < 3 * per_axis; t += 64 * TY) {
-    const int ax = t / per_axis, r = t - ax * per_axis;
-    const int a = r / nc, c = r - a * nc;
-    const int i = ax * kMaxClasses * kMaxClasses + a * kMaxClasses + c;
-    sm.cf[i] = src[i];
-  }
-  if ((int)threadIdx.x < nc) sm.cls[threadIdx.x] = tab->cls[threadIdx.x];
-}
 
 // March one tile (tz, ty) over the x-chunk [tx*xc, tx*xc + xc) of one grid.
 // Tables must be staged (a barrier inside the march orders them).  The
@@ -240,7 +199,7 @@ __device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& 
       st_f32(nl, c.r.lo_out, c.col * 4, so * 4);
       st_f32(om, c.r.om, c.col * 4, so * 4);
       if (nlab != P.b)
-        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)nlab, c.r.lab, (int)c.col, so, 0);
+        st_u8(nlab, c.r.lab, c.col, so);
     }
     hm = P.h;
     lm = P.l;
@@ -259,29 +218,7 @@ __device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& 
     if (x + 3 < c.x1) plane_step(I3{}, I1{}, x + 3);
   }
 
-  if (partials) {
-    const float pe = wave_sum(acc.perf);
-    const float bn = wave_sum(acc.bnd);
-    const unsigned mo = wave_sum_u(acc.mono);
-    if (lane == 0) {
-      sm.red[0][wy] = pe;
-      sm.red[1][wy] = bn;
-      sm.red[2][wy] = (float)mo;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-      for (int w = 0; w < TY; ++w) {
-        a0 += sm.red[0][w];
-        a1 += sm.red[1][w];
-        a2 += sm.red[2][w];
-      }
-      float* out = partials + (size_t)wg_slot * 3;
-      out[0] = a0;
-      out[1] = a1;
-      out[2] = a2;
-    }
-  }
+  if (partials) write_partials(acc, &sm.red[0][0], TY, partials + (size_t)wg_slot * 3);
 }
 
 }  // namespace
@@ -291,7 +228,7 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled(StepBuffers b, StepConst
                                                         int ny, int nz, int xc, int tiles_z,
                                                         int tiles_y, int nwg) {
   __shared__ TileSmem<TY> sm;
-  stage_tables<TY>(sm, b.tab, b.n_classes);
+  stage_tables(sm.cf, sm.cls, b.tab, b.n_classes, 64 * TY);
   const int wg = remap_xcd(blockIdx.x, nwg);
   const int tz = wg % tiles_z;
   const int ty = (wg / tiles_z) % tiles_y;
@@ -344,7 +281,7 @@ __global__ __launch_bounds__(64 * TY) void k_step_batch(const BatchInstance* ins
     K.clamp2 = uf(I.K.clamp2);
     K.cap = uf(I.K.cap);
     K.thr = uf(I.K.thr);
-    stage_tables<TY>(sm, b.tab, b.n_classes);
+    stage_tables(sm.cf, sm.cls, b.tab, b.n_classes, 64 * TY);
     tile_march<TY>(sm, b, K, PERF, ui(I.nx), ui(I.ny), ui(I.nz), ui(I.xc), ui(w.tz), ui(w.ty),
                    ui(w.tx), partials, it);
   };

@@ -179,6 +179,62 @@ def test_tiled_kernel_bitwise_equals_reference(shape, ty, xc):
     g2.close()
 
 
+@pytest.mark.parametrize("shape,ty,xc,perf", [((40, 37, 70), 8, 3, False),
+                                              ((33, 70, 129), 16, 5, True),
+                                              ((21, 45, 64), 8, 7, False),
+                                              ((64, 64, 62), 8, 64, True),
+                                              ((5, 66, 131), 16, 4, False),
+                                              ((9, 5, 3), 8, 4, False)])
+def test_two_step_kernel_bitwise_equals_reference(shape, ty, xc, perf):
+    """Temporal blocking (two steps per launch, overlapped halo) against the
+    one-thread-per-voxel reference: identical states, damage and latches
+    after odd and even step counts (an odd count ends with one single
+    step), with and without a perfusion field, on ragged tiles."""
+    from paper_1907_05709_amd import rfa
+    case = W.random_tissue_case(70 + ty + xc, shape=shape, n_classes=5, n_tines=2, n_steps=40)
+    field = None
+    if perf:
+        field = np.random.default_rng(71).uniform(0.5, 2.0, shape).astype(np.float32)
+    grids = []
+    for kw in (dict(kernel=1), dict(kernel=2, depth=2, tile_y=ty, tile_x=xc)):
+        g = rfa.Grid(case.shape, case.spacing, t_death=case.t_death, A=case.arrhenius_a,
+                     Ea=case.arrhenius_ea, R=case.gas_r, omega_cap=case.omega_cap, **kw)
+        g.load_case(case)
+        if field is not None:
+            g.set_perfusion(field)
+        grids.append(g)
+    g1, g2 = grids
+    plan = g2.plan()
+    assert plan["depth"] == 2 and plan["tile_y"] == ty and plan["tile_x"] == min(xc, shape[0])
+    dt = 0.9 * min(case.dt, g1.dt_max())
+    for n in (1, 6, 33):
+        d1 = g1.step(n, dt, diag=True)
+        d2 = g2.step(n, dt, diag=True)
+        assert np.array_equal(g1.temperature(), g2.temperature()), n
+        m1, o1, _ = g1.damage()
+        m2, o2, _ = g2.damage()
+        assert np.array_equal(m1, m2) and np.array_equal(o1, o2), n
+        assert d1["mono_violations"] == d2["mono_violations"]
+        assert d1["energy_J"] == d2["energy_J"]
+        scale = abs(d1["injected_J"]) + abs(d1["perfusion_J"]) + abs(d1["boundary_J"])
+        for k in ("perfusion_J", "boundary_J"):
+            assert abs(d1[k] - d2[k]) <= 1e-6 * scale, (k, d1[k], d2[k], scale)
+    for a1, a2 in zip(g1.raw_state(), g2.raw_state()):
+        assert np.array_equal(a1, a2)
+    g1.close()
+    g2.close()
+
+
+def test_two_step_kernel_matches_oracle_on_the_straight_recipe():
+    case = W.case_straight(n=64, n_steps=301, seed=2003)
+    g, T, mask, om, _, d = parity.gpu_run(case, depth=2)
+    assert g.plan()["depth"] == 2
+    ost, _, _ = O.run(case)
+    err = parity.compare(case, T, mask, om, ost)
+    print(f"two-step 64^3 x 301: max|dT| = {err:.3e} K")
+    g.close()
+
+
 def test_tune_keeps_state_and_timing_counts_launches():
     from paper_1907_05709_amd import rfa
     case = W.case_straight(n=48, n_steps=20, seed=2005)
@@ -195,7 +251,8 @@ def test_tune_keeps_state_and_timing_counts_launches():
     g.kernel_stats()
     g.step(7, case.dt, diag=False)
     ms, n, vs = g.kernel_stats()
-    assert n == 7 and vs == 7 * case.n_voxels and ms > 0.0
+    depth = plan["depth"]      # timed: the plan's launches, not a trailing single step
+    assert n == 7 // depth and vs == n * depth * case.n_voxels and ms > 0.0
     assert rfa.rfa_copy_bandwidth(1 << 26, 3) > 100.0
     g.close()
 
