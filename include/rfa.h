@@ -118,6 +118,9 @@ typedef struct {
   int time_kernels;   /* N > 0: time step-kernel launches with HIP events,
                          one event pair per block of N consecutive launches
                          (read with rfa_kernel_stats); 0 = off (0)           */
+  int z_vec;          /* tiled one-step kernel: consecutive z voxels per
+                         lane, 1, 2 or 4 (2 and 4 need nz divisible by it,
+                         tile_y 4 or 8; otherwise 1 is used); 0 = auto (0)   */
 } rfa_options;
 
 /* Diagnostics of one rfa_step call (energies relative to 37 degC, J). */
@@ -198,9 +201,10 @@ rfa_status rfa_kernel_stats(rfa_grid g, double* kernel_ms, long long* launches,
                             long long* voxel_steps);
 
 /* Current launch plan: kernel (1 reference, 2 tiled), steps per launch,
- * tile rows, x planes per work-group, work-groups per launch. */
+ * tile rows, x planes per work-group, work-groups per launch, z voxels per
+ * lane. */
 rfa_status rfa_get_plan(rfa_grid g, int* kernel, int* depth, int* tile_y, int* tile_x,
-                        int* workgroups);
+                        int* workgroups, int* z_vec);
 
 /* Time the candidate launch plans of this grid's shape on scratch copies of
  * its state (the state is not advanced) and keep the fastest per step: the

@@ -20,6 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "librfa.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 SOURCES = ["rfa_api.hip", "rfa_kernels.hip", "rfa_step.hip", "rfa_tiled.hip", "rfa_tiled2.hip",
+           "rfa_wide.hip",
            "rfa_adjoint.hip"]
 ARCH = "gfx950"
 

@@ -475,6 +475,7 @@ rfa_status rfa_default_options(rfa_options* opt) {
   opt->tile_y = 0;
   opt->tile_x = 0;
   opt->time_kernels = 0;
+  opt->z_vec = 0;
   return RFA_OK;
 }
 
@@ -502,6 +503,8 @@ rfa_status rfa_create_grid(int nx, int ny, int nz, double dx, double dy, double 
   if (o.tile_y != 0 && o.tile_y != 4 && o.tile_y != 8 && o.tile_y != 16)
     return fail(RFA_ERR_ARG, "tile_y must be 0, 4, 8 or 16");
   if (o.tile_x < 0) return fail(RFA_ERR_ARG, "tile_x must be >= 0");
+  if (o.z_vec != 0 && o.z_vec != 1 && o.z_vec != 2 && o.z_vec != 4)
+    return fail(RFA_ERR_ARG, "z_vec must be 0, 1, 2 or 4");
   if (o.time_kernels < 0 || o.time_kernels > kTimedBatch)
     return fail(RFA_ERR_ARG, "time_kernels must be in 0..%d", kTimedBatch);
   rfa_grid g = new (std::nothrow) rfa_grid_s();
@@ -517,7 +520,7 @@ rfa_status rfa_create_grid(int nx, int ny, int nz, double dx, double dy, double 
     return fail(RFA_ERR_HIP, "no HIP device");
   }
   const size_t n = g->g.n();
-  g->plan = plan_default(g->g, o.kernel, o.depth, o.tile_y, o.tile_x);
+  g->plan = plan_default(g->g, o.kernel, o.depth, o.tile_y, o.tile_x, o.z_vec);
   const size_t nwg = (size_t)plan_max_wg(g->g);
   g->partial_floats = nwg * 3 * kPartialSlots;
   g->red_doubles = 4 * 1024 + 64;
@@ -933,13 +936,14 @@ rfa_status rfa_kernel_stats(rfa_grid g, double* kernel_ms, long long* launches,
 }
 
 rfa_status rfa_get_plan(rfa_grid g, int* kernel, int* depth, int* tile_y, int* tile_x,
-                        int* workgroups) {
+                        int* workgroups, int* z_vec) {
   if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
   if (kernel) *kernel = g->plan.kind;
   if (depth) *depth = g->plan.depth;
   if (tile_y) *tile_y = g->plan.ty;
   if (tile_x) *tile_x = g->plan.xc;
   if (workgroups) *workgroups = g->plan.nwg;
+  if (z_vec) *z_vec = g->plan.zv;
   return RFA_OK;
 }
 
@@ -983,8 +987,8 @@ rfa_status rfa_tune(rfa_grid g, double dt, int reps) {
   if ((s = dmalloc(&om2, n)) != RFA_OK) return s;
   if ((s = dmalloc(&lab2, n)) != RFA_OK) { (void)hipFree(om2); return s; }
   if ((s = ensure_events(g, 2)) != RFA_OK) { (void)hipFree(om2); (void)hipFree(lab2); return s; }
-  StepPlan cand[32];
-  const int nc = plan_candidates(g->g, g->opt.depth == 1 ? 1 : kMaxDepth, cand, 32);
+  StepPlan cand[64];
+  const int nc = plan_candidates(g->g, g->opt.depth == 1 ? 1 : kMaxDepth, cand, 64);
   const StepConst K = step_const(g, dt);
   StepBuffers b;
   b.hi_in = g->hi[g->cur];

@@ -20,19 +20,21 @@ struct StepPlan {
   int ty;      // tile rows (y) per work-group (tiled)
   int xc;      // x planes per work-group (tiled)
   int nwg;     // work-groups per launch (stride of the partials)
+  int zv;      // consecutive z voxels per lane (tiled, one step per launch)
   // one-step plan for step counts not divisible by depth (equal to the
   // plan itself when depth == 1)
-  int one_kind, one_ty, one_xc, one_nwg;
+  int one_kind, one_ty, one_xc, one_nwg, one_zv;
 };
 
 StepPlan plan_naive(Grid3 g);
 StepPlan plan_tiled(Grid3 g, int ty, int xc);
 StepPlan plan_tiled2(Grid3 g, int ty, int xc);
+StepPlan plan_wide(Grid3 g, int zv, int ty, int xc);
 // The one-step plan that accompanies a plan.
 StepPlan plan_one(const StepPlan& p);
-// Heuristic plan from the options (kernel, depth, tile_y, tile_x; 0 =
-// automatic).
-StepPlan plan_default(Grid3 g, int kernel, int depth, int tile_y, int tile_x);
+// Heuristic plan from the options (kernel, depth, tile_y, tile_x, z_vec;
+// 0 = automatic).
+StepPlan plan_default(Grid3 g, int kernel, int depth, int tile_y, int tile_x, int zv);
 // Candidate plans for tuning (depth 1, and depth 2 if max_depth >= 2).
 int plan_candidates(Grid3 g, int max_depth, StepPlan* out, int max_out);
 // Largest partial stride any plan of this grid can need.

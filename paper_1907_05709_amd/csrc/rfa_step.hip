@@ -17,14 +17,19 @@ StepPlan with_one(StepPlan p, const StepPlan& one) {
   p.one_ty = one.ty;
   p.one_xc = one.xc;
   p.one_nwg = one.nwg;
+  p.one_zv = one.zv;
   return p;
 }
 
-// x chunk giving about kTargetWg work-groups for `tiles` tiles per plane
-int default_xc(Grid3 g, int tiles) {
-  const int chunks = std::max(1, (kTargetWg + tiles - 1) / tiles);
+// x chunk giving about `target` work-groups for `tiles` tiles per plane
+int default_xc(Grid3 g, int tiles, int target = kTargetWg) {
+  const int chunks = std::max(1, (target + tiles - 1) / tiles);
   return std::min(g.nx, std::max(4, (g.nx + chunks - 1) / chunks));
 }
+
+// Work-groups that fit the chip at once with the wide kernel (4-wave
+// work-groups, 2 resident waves per SIMD with 4 voxels per lane, 4 with 2).
+int wide_target_wg(int zv) { return zv == 4 ? 512 : 1024; }
 }  // namespace
 
 StepPlan plan_naive(Grid3 g) {
@@ -34,6 +39,7 @@ StepPlan plan_naive(Grid3 g) {
   p.ty = 4;
   p.xc = 1;
   p.nwg = naive_wg_count(g);
+  p.zv = 1;
   return with_one(p, p);
 }
 
@@ -45,6 +51,19 @@ StepPlan plan_tiled(Grid3 g, int ty, int xc) {
   p.ty = ty;
   p.xc = xc;
   p.nwg = s.nwg;
+  p.zv = 1;
+  return with_one(p, p);
+}
+
+StepPlan plan_wide(Grid3 g, int zv, int ty, int xc) {
+  const TiledShape s = wide_shape(g, zv, ty, xc);
+  StepPlan p;
+  p.kind = kStepTiled;
+  p.depth = 1;
+  p.ty = ty;
+  p.xc = xc;
+  p.nwg = s.nwg;
+  p.zv = zv;
   return with_one(p, p);
 }
 
@@ -56,7 +75,8 @@ StepPlan plan_tiled2(Grid3 g, int ty, int xc) {
   p.ty = ty;
   p.xc = xc;
   p.nwg = s.nwg;
-  return with_one(p, plan_default(g, kStepTiled, 1, 0, 0));
+  p.zv = 1;
+  return with_one(p, plan_default(g, kStepTiled, 1, 0, 0, 0));
 }
 
 StepPlan plan_one(const StepPlan& p) {
@@ -66,11 +86,21 @@ StepPlan plan_one(const StepPlan& p) {
   o.ty = p.one_ty;
   o.xc = p.one_xc;
   o.nwg = p.one_nwg;
+  o.zv = p.one_zv;
   return o;
 }
 
-StepPlan plan_default(Grid3 g, int kernel, int depth, int tile_y, int tile_x) {
+StepPlan plan_default(Grid3 g, int kernel, int depth, int tile_y, int tile_x, int zv) {
   if (kernel == kStepNaive || !tiled_fits(g, 4)) return plan_naive(g);
+  // automatic: four z voxels per lane once a tile row spans 256 voxels
+  if (zv == 0 && depth != 2 && g.nz >= 256 && g.nz % 4 == 0) zv = 4;
+  if (depth != 2 && (zv == 2 || zv == 4) && wide_fits(g, zv, 4) && tile_y != 16) {
+    const int ty = tile_y ? tile_y : 4;
+    const int tiles = ((g.nz + 64 * zv - 1) / (64 * zv)) * ((g.ny + ty - 1) / ty);
+    int xc = tile_x ? std::min(tile_x, g.nx) : default_xc(g, tiles, wide_target_wg(zv));
+    while (xc > 4 && !wide_fits(g, zv, xc)) xc /= 2;
+    return plan_wide(g, zv, ty, xc);
+  }
   if (depth == 2 && tiled2_fits(g, 4)) {
     const int ty = tile_y == 16 ? 16 : 8;
     const int tiles = ((g.nz + 61) / 62) * ((g.ny + ty - 3) / (ty - 2));
@@ -96,6 +126,16 @@ int plan_candidates(Grid3 g, int max_depth, StepPlan* out, int max_out) {
       if ((xc > g.nx && xc != 4) || !tiled_fits(g, std::min(xc, g.nx))) continue;
       out[n++] = plan_tiled(g, ty, std::min(xc, g.nx));
     }
+  const int zvs[] = {2, 4};
+  const int tysw[] = {4, 8};
+  const int xcsw[] = {4, 8, 16, 32, 64};
+  for (int zv : zvs)
+    for (int ty : tysw)
+      for (int xc : xcsw) {
+        if (n >= max_out) return n;
+        if ((xc > g.nx && xc != 4) || !wide_fits(g, zv, std::min(xc, g.nx))) continue;
+        out[n++] = plan_wide(g, zv, ty, std::min(xc, g.nx));
+      }
   if (max_depth < 2) return n;
   const int tys2[] = {8, 16};
   for (int ty : tys2)
@@ -119,6 +159,8 @@ hipError_t launch_plan(Grid3 g, const StepPlan& plan, const StepBuffers& b, cons
                        hipStream_t st) {
   if (plan.kind == kStepNaive) return launch_step_naive(g, b, K, st);
   if (plan.depth == 2) return launch_step_tiled2(tiled2_shape(g, plan.ty, plan.xc), g, b, K, st);
+  if (plan.zv > 1)
+    return launch_step_wide(plan.zv, wide_shape(g, plan.zv, plan.ty, plan.xc), g, b, K, st);
   return launch_step_tiled(tiled_shape(g, plan.ty, plan.xc), g, b, K, st);
 }
 

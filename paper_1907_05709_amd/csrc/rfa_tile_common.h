@@ -12,6 +12,11 @@ namespace rfa {
 namespace tile {
 
 constexpr int kRsrcWord3 = 0x00020000;  // gfx9 buffer descriptor word 3 (32-bit data format)
+// A vector offset at or beyond a descriptor's record count makes a buffer
+// load return 0 and a buffer store do nothing; descriptors here never span
+// 2^31 bytes, so this offset (plus any in-range scalar offset) is always
+// out of range.  Used to predicate stores without a branch.
+constexpr unsigned kOob = 0x80000000u;
 
 // Hardware places work-group w on XCD w % 8.  Give XCD k the contiguous range
 // of logical tiles [base_k, base_k + count_k), so tiles sharing halo rows

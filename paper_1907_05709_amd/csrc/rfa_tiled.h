@@ -51,6 +51,13 @@ bool tiled_fits(Grid3 g, int xc);
 hipError_t launch_step_tiled(const TiledShape& s, Grid3 g, const StepBuffers& b,
                              const StepConst& K, hipStream_t st);
 
+// One step with zv (2 or 4) consecutive z voxels per lane, ty = 4 or 8;
+// needs nz % zv == 0.
+TiledShape wide_shape(Grid3 g, int zv, int ty, int xc);
+bool wide_fits(Grid3 g, int zv, int xc);
+hipError_t launch_step_wide(int zv, const TiledShape& s, Grid3 g, const StepBuffers& b,
+                            const StepConst& K, hipStream_t st);
+
 // Two steps per launch (temporal blocking, ty = 8 or 16): tiles own
 // 62 x (ty - 2) columns and recompute a one-voxel rim of the first step.
 // The partials receive the sums of both steps.

@@ -11,7 +11,13 @@
 // source increment, damage integral) are issued while plane x is computed,
 // into a ring of kSlots register sets.  The x loop is unrolled kSlots times
 // so every ring index is a compile-time constant (no register moves).  One
-// barrier per plane.
+// barrier per plane.  Every pass of the unrolled loop computes all kSlots
+// planes and issues the same loads and stores, whatever the chunk length:
+// planes past the chunk's end are computed as held voxels and their stores
+// (like those of lanes outside the grid, and unchanged latch bytes) get an
+// out-of-range buffer offset, which the hardware drops.  With no branch
+// around a memory instruction, the compiler's wait counts stay exact and a
+// plane waits only for its own loads, not for the ones in flight behind it.
 //
 // Addressing: every array is accessed through a buffer descriptor whose
 // base is the first plane the work-group touches; a lane adds a fixed
@@ -169,6 +175,8 @@ __device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& 
 
   Partial acc{0.0f, 0.0f, 0u};
   const int me = (wy + 1) * W + lane + 1;  // own LDS cell
+  const unsigned st4 = inside ? c.col * 4 : kOob;  // store offsets (out of range: dropped)
+  const unsigned st1 = inside ? c.col : kOob;
 
   // One plane; S = ring slot of plane x (compile time), BUF = LDS buffer.
   auto plane_step = [&](auto S_, auto BUF_, int x) {
@@ -190,16 +198,18 @@ __device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& 
     const Plane& N = q[SN];
     float nh, nl, om = P.om;
     unsigned nlab;
-    voxel_step(P.h, P.l, P.b, hm, lm, bm, N.h, N.l, N.b, ym.x, ym.y, bym, yp.x, yp.y, byp,
+    const bool valid = x < c.x1;                        // uniform
+    const unsigned lab = valid ? P.b : (P.b | kHeld);   // past the chunk: no contributions
+    voxel_step(P.h, P.l, lab, hm, lm, bm, N.h, N.l, N.b, ym.x, ym.y, bym, yp.x, yp.y, byp,
                zm.x, zm.y, bzm, zp.x, zp.y, bzp, P.s, P.pf, om, sm.cf, sm.cls, K, nh, nl, nlab,
                acc);
-    if (inside) {
-      const int so = (x - c.xb) * (int)c.psz;  // uniform
-      st_f32(nh, c.r.hi_out, c.col * 4, so * 4);
-      st_f32(nl, c.r.lo_out, c.col * 4, so * 4);
-      st_f32(om, c.r.om, c.col * 4, so * 4);
-      if (nlab != P.b)
-        st_u8(nlab, c.r.lab, c.col, so);
+    {
+      const int so = (min(x, c.x1 - 1) - c.xb) * (int)c.psz;  // uniform
+      const unsigned v4 = valid ? st4 : kOob;
+      st_f32(nh, c.r.hi_out, v4, so * 4);
+      st_f32(nl, c.r.lo_out, v4, so * 4);
+      st_f32(om, c.r.om, v4, so * 4);
+      st_u8(nlab, c.r.lab, (valid && nlab != P.b) ? st1 : kOob, so);
     }
     hm = P.h;
     lm = P.l;
@@ -213,9 +223,9 @@ __device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& 
   // kSlots is even, so plane x uses LDS buffer (x - x0) & 1 = slot & 1.
   for (int x = x0; x < c.x1; x += kSlots) {
     plane_step(I0{}, I0{}, x);
-    if (x + 1 < c.x1) plane_step(I1{}, I1{}, x + 1);
-    if (x + 2 < c.x1) plane_step(I2{}, I0{}, x + 2);
-    if (x + 3 < c.x1) plane_step(I3{}, I1{}, x + 3);
+    plane_step(I1{}, I1{}, x + 1);
+    plane_step(I2{}, I0{}, x + 2);
+    plane_step(I3{}, I1{}, x + 3);
   }
 
   if (partials) write_partials(acc, &sm.red[0][0], TY, partials + (size_t)wg_slot * 3);

@@ -203,8 +203,10 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled2(StepBuffers b, StepCons
       acc.mono += own1 ? p1.mono : 0u;
     }
 
-    // second step, plane j - 1, stored by the owners
-    if (j > x0) {
+    // second step, plane j - 1, stored by the owners while it lies in the
+    // chunk (every pass issues the same memory instructions; see below)
+    {
+      const bool keep = owner && j > x0 && j <= x1;
       const float2 ym = sm.t1[1 - BUF][me - W], yp = sm.t1[1 - BUF][me + W];
       const float2 zm = sm.t1[1 - BUF][me - 1], zp = sm.t1[1 - BUF][me + 1];
       const unsigned bym = sm.b1[1 - BUF][me - W], byp = sm.b1[1 - BUF][me + W];
@@ -216,16 +218,15 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled2(StepBuffers b, StepCons
       voxel_step(h1p, l1p, b1p, h1pp, l1pp, b1pp, h1, l1, b1, ym.x, ym.y, bym, yp.x, yp.y, byp,
                  zm.x, zm.y, bzm, zp.x, zp.y, bzp, Q.s, Q.pf, om2, sm.cf, sm.cls, K, h2, l2, b2,
                  p2);
-      if (owner) {
-        const int so = (j - 1 - xb) * (int)psz;  // uniform
-        st_f32(h2, r_hio, col * 4, so * 4);
-        st_f32(l2, r_loo, col * 4, so * 4);
-        st_f32(om2, r_om, col * 4, so * 4);
-        if (b2 != Q.b) st_u8(b2, r_lab, col, so);
-      }
-      acc.perf += owner ? p2.perf : 0.0f;
-      acc.bnd += owner ? p2.bnd : 0.0f;
-      acc.mono += owner ? p2.mono : 0u;
+      const int so = (min(max(j - 1, x0), x1 - 1) - xb) * (int)psz;  // uniform
+      const unsigned v4 = keep ? col * 4 : kOob;
+      st_f32(h2, r_hio, v4, so * 4);
+      st_f32(l2, r_loo, v4, so * 4);
+      st_f32(om2, r_om, v4, so * 4);
+      st_u8(b2, r_lab, (keep && b2 != Q.b) ? col : kOob, so);
+      acc.perf += keep ? p2.perf : 0.0f;
+      acc.bnd += keep ? p2.bnd : 0.0f;
+      acc.mono += keep ? p2.mono : 0u;
     }
     h1pp = h1p;
     l1pp = l1p;
@@ -243,12 +244,16 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled2(StepBuffers b, StepCons
   using I2 = std::integral_constant<int, 2>;
   using I3 = std::integral_constant<int, 3>;
   static_assert(kRing2 == 4, "unrolled for a ring of four planes");
-  // planes x0 - 1 .. x1: plane x0 - 1 + k uses ring slot k % 4 and LDS buffer k & 1
+  // Planes x0 - 1 .. x1: plane x0 - 1 + k uses ring slot k % 4 and LDS buffer
+  // k & 1.  Every pass runs all four planes and issues the same loads and
+  // stores: stores outside the chunk or by non-owners get an out-of-range
+  // buffer offset (dropped by the hardware), so no branch surrounds a memory
+  // instruction and the compiler's wait counts stay exact.
   for (int j = x0 - 1; j <= x1; j += kRing2) {
     iter(I0{}, I0{}, j);
-    if (j + 1 <= x1) iter(I1{}, I1{}, j + 1);
-    if (j + 2 <= x1) iter(I2{}, I0{}, j + 2);
-    if (j + 3 <= x1) iter(I3{}, I1{}, j + 3);
+    iter(I1{}, I1{}, j + 1);
+    iter(I2{}, I0{}, j + 2);
+    iter(I3{}, I1{}, j + 3);
   }
 
   if (b.partials) write_partials(acc, sm.red, TY, b.partials + (size_t)wg * 3);

@@ -48,7 +48,8 @@ class rfa_options(C.Structure):
     _fields_ = [("t_death", C.c_double), ("A", C.c_double), ("Ea", C.c_double),
                 ("R", C.c_double), ("omega_cap", C.c_double), ("stream", C.c_void_p),
                 ("inputs_on_device", C.c_int), ("depth", C.c_int), ("kernel", C.c_int),
-                ("tile_y", C.c_int), ("tile_x", C.c_int), ("time_kernels", C.c_int)]
+                ("tile_y", C.c_int), ("tile_x", C.c_int), ("time_kernels", C.c_int),
+                ("z_vec", C.c_int)]
 
 
 class rfa_diag(C.Structure):
@@ -79,7 +80,7 @@ _SIGS = {
     "rfa_get_step_count": [C.c_void_p, C.POINTER(C.c_longlong)],
     "rfa_kernel_stats": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
                          C.POINTER(C.c_longlong)],
-    "rfa_get_plan": [C.c_void_p] + [C.POINTER(C.c_int)] * 5,
+    "rfa_get_plan": [C.c_void_p] + [C.POINTER(C.c_int)] * 6,
     "rfa_tune": [C.c_void_p, C.c_double, C.c_int],
     "rfa_copy_bandwidth": [C.c_size_t, C.c_int, C.POINTER(C.c_double)],
     "rfa_set_perfusion_bspline": [C.c_void_p, C.c_int, C.c_void_p],
@@ -259,9 +260,10 @@ def rfa_kernel_stats(g):
 
 
 def rfa_get_plan(g):
-    v = [C.c_int() for _ in range(5)]
+    v = [C.c_int() for _ in range(6)]
     _check(lib().rfa_get_plan(g, *[C.byref(x) for x in v]))
-    return dict(zip(("kernel", "depth", "tile_y", "tile_x", "workgroups"), [x.value for x in v]))
+    return dict(zip(("kernel", "depth", "tile_y", "tile_x", "workgroups", "z_vec"),
+                    [x.value for x in v]))
 
 
 def rfa_tune(g, dt: float, reps: int = 20):
@@ -359,7 +361,7 @@ class Grid:
 
     def __init__(self, shape, spacing, device: bool = False, depth: int = 0,
                  stream=None, kernel: int = 0, tile_y: int = 0, tile_x: int = 0,
-                 time_kernels: int = 0, **damage):
+                 time_kernels: int = 0, z_vec: int = 0, **damage):
         self.shape = tuple(int(s) for s in shape)
         self.spacing = tuple(float(s) for s in spacing)
         self.device = bool(device)
@@ -372,6 +374,7 @@ class Grid:
         opt.tile_y = int(tile_y)
         opt.tile_x = int(tile_x)
         opt.time_kernels = int(time_kernels)
+        opt.z_vec = int(z_vec)
         if stream is not None:
             opt.stream = C.c_void_p(int(stream))
         elif self.device:

@@ -225,6 +225,59 @@ def test_two_step_kernel_bitwise_equals_reference(shape, ty, xc, perf):
     g2.close()
 
 
+@pytest.mark.parametrize("shape,zv,ty,xc,perf", [((40, 37, 72), 4, 4, 3, False),
+                                                 ((33, 70, 130), 2, 8, 5, True),
+                                                 ((21, 45, 256), 4, 8, 7, True),
+                                                 ((16, 20, 300), 4, 4, 8, False),
+                                                 ((9, 6, 8), 2, 4, 4, False)])
+def test_wide_kernel_bitwise_equals_reference(shape, zv, ty, xc, perf):
+    """Several z voxels per lane (vector loads, wide tiles with a z halo
+    between tiles when nz exceeds a tile row) against the reference kernel:
+    identical states, damage, latches."""
+    from paper_1907_05709_amd import rfa
+    case = W.random_tissue_case(90 + zv + xc, shape=shape, n_classes=5, n_tines=2, n_steps=40)
+    field = None
+    if perf:
+        field = np.random.default_rng(91).uniform(0.5, 2.0, shape).astype(np.float32)
+    grids = []
+    for kw in (dict(kernel=1), dict(kernel=2, depth=1, z_vec=zv, tile_y=ty, tile_x=xc)):
+        g = rfa.Grid(case.shape, case.spacing, t_death=case.t_death, A=case.arrhenius_a,
+                     Ea=case.arrhenius_ea, R=case.gas_r, omega_cap=case.omega_cap, **kw)
+        g.load_case(case)
+        if field is not None:
+            g.set_perfusion(field)
+        grids.append(g)
+    g1, g2 = grids
+    plan = g2.plan()
+    assert plan["z_vec"] == zv and plan["tile_y"] == ty and plan["tile_x"] == min(xc, shape[0])
+    dt = 0.9 * min(case.dt, g1.dt_max())
+    for n in (1, 6, 33):
+        d1 = g1.step(n, dt, diag=True)
+        d2 = g2.step(n, dt, diag=True)
+        assert np.array_equal(g1.temperature(), g2.temperature()), n
+        m1, o1, _ = g1.damage()
+        m2, o2, _ = g2.damage()
+        assert np.array_equal(m1, m2) and np.array_equal(o1, o2), n
+        assert d1["mono_violations"] == d2["mono_violations"]
+        assert d1["energy_J"] == d2["energy_J"]
+        scale = abs(d1["injected_J"]) + abs(d1["perfusion_J"]) + abs(d1["boundary_J"])
+        for k in ("perfusion_J", "boundary_J"):
+            assert abs(d1[k] - d2[k]) <= 1e-6 * scale, (k, d1[k], d2[k], scale)
+    for a1, a2 in zip(g1.raw_state(), g2.raw_state()):
+        assert np.array_equal(a1, a2)
+    g1.close()
+    g2.close()
+
+
+def test_wide_kernel_needs_divisible_rows():
+    """A grid whose z extent is not a multiple of the vector width keeps the
+    one-voxel-per-lane kernel."""
+    from paper_1907_05709_amd import rfa
+    g = rfa.Grid((10, 10, 13), (1e-3,) * 3, z_vec=4)
+    assert g.plan()["z_vec"] == 1
+    g.close()
+
+
 def test_two_step_kernel_matches_oracle_on_the_straight_recipe():
     case = W.case_straight(n=64, n_steps=301, seed=2003)
     g, T, mask, om, _, d = parity.gpu_run(case, depth=2)
