@@ -26,8 +26,14 @@ hipError_t launch_bspline_grad(Grid3 g, const float* gf, const float* f, int m,
                                double* gctrl, hipStream_t st);
 hipError_t launch_adjoint_weight(Grid3 g, const float* w, const float* om, const uint8_t* lab,
                                  float cap, float* wa, hipStream_t st);
+// Reference adjoint step (one thread per voxel).
 hipError_t launch_adjoint_step(Grid3 g, const AdjointBuffers& a, const StepConst& K,
                                hipStream_t st);
+// The same step with the tiled schedule (ty = 4 or 8 rows, xc x planes per
+// work-group); bitwise equal to the reference.
+bool adjoint_tiled_fits(Grid3 g, int xc);
+hipError_t launch_adjoint_tiled(Grid3 g, int ty, int xc, const AdjointBuffers& a,
+                                const StepConst& K, hipStream_t st);
 // partial[t * nblk + b]: per-block sums of g_t(p) sacc_p dt / (rho c)_p.
 hipError_t launch_source_dot(Grid3 g, double dx, double dy, double dz, const uint8_t* lab,
                              const Chord* chords, const int* tine_first, int n_tines,

@@ -21,13 +21,20 @@
 #include <math.h>
 
 #include "rfa_adjoint.h"
+#include "rfa_tile_common.h"
+#include "rfa_tiled.h"
+
+#include <type_traits>
 
 namespace rfa {
 
 namespace {
 
-__device__ __forceinline__ float coef(const Tables* T, int axis, unsigned a, unsigned b) {
-  const float2 c = T->cf[axis][(a & kClassMask) * kMaxClasses + (b & kClassMask)];
+// Conduction coefficient C(a, b) along an axis from a coefficient table laid
+// out as Tables::cf, summed from its float-float parts.
+__device__ __forceinline__ float coef(const float2* cf, int axis, unsigned a, unsigned b) {
+  const float2 c =
+      cf[axis * kMaxClasses * kMaxClasses + (a & kClassMask) * kMaxClasses + (b & kClassMask)];
   return c.x + c.y;
 }
 
@@ -155,8 +162,49 @@ hipError_t launch_adjoint_weight(Grid3 g, const float* w, const float* om, const
   return hipGetLastError();
 }
 
-// One adjoint step: lam_out = M^T lam_in + w' dt rate'(theta^n); accumulates
-// dL/ds (sacc += lam_in) and dL/df (facc += lam_in (-B theta^n)) on free voxels.
+// Adjoint update of one voxel q: lam_out = (M^T lam_in)_q + w_q dt rate'(theta^n_q),
+// and the accumulations sacc += lam_in_q, facc += lam_in_q (-B theta^n_q), for
+// a free voxel; a held voxel gets lam_out = 0 and accumulates nothing
+// (returns false).  Neighbours in the order x-, x+, y-, y+, z-, z+; cf and
+// cls point at the coefficient tables (global or LDS copy, same layout).
+__device__ __forceinline__ bool adjoint_voxel(float lam, float th, unsigned lq, float pf,
+                                              float w, const float (&nlam)[6],
+                                              const unsigned (&nlab)[6],
+                                              const float2* __restrict__ cf,
+                                              const float4* __restrict__ cls,
+                                              const StepConst& K, float& lam_out,
+                                              float& sacc, float& facc) {
+  if (lq & kHeld) {
+    lam_out = 0.0f;
+    return false;
+  }
+  const float4 cl = cls[lq & kClassMask];
+  const float B = (cl.x + cl.y) * pf;
+  float diag = 1.0f - B;
+  float off = 0.0f;
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const unsigned lp = nlab[f];
+    diag -= coef(cf, f >> 1, lq, lp);                  // q's own row
+    if (!(lp & kHeld)) off = __builtin_fmaf(coef(cf, f >> 1, lp, lq), nlam[f], off);
+  }
+  // damage-rate derivative at theta^n (zero where the exponent is capped)
+  float dr = 0.0f;
+  if (lq & kTissue) {
+    const float tk = K.tak + th;
+    const float x = K.c2 * th / tk;
+    if (x < K.clamp2) {
+      const float rate = K.dtka * __builtin_amdgcn_exp2f(x);
+      dr = rate * (K.c2 * 0.69314718f) * K.tak / (tk * tk);
+    }
+  }
+  lam_out = __builtin_fmaf(diag, lam, off) + w * dr;
+  sacc += lam;
+  facc = __builtin_fmaf(-cl.x - cl.y, th * lam, facc);
+  return true;
+}
+
+// Reference adjoint step, one thread per voxel.
 __global__ __launch_bounds__(256) void k_adjoint_step(AdjointBuffers a, StepConst K, int nx,
                                                       int ny, int nz) {
   const int k = blockIdx.x * 64 + threadIdx.x;
@@ -170,39 +218,216 @@ __global__ __launch_bounds__(256) void k_adjoint_step(AdjointBuffers a, StepCons
     a.lam_out[q] = 0.0f;
     return;
   }
-  const Tables* T = a.tab;
-  const float lam = a.lam_in[q];
-  const float th = a.theta[q];
-  const float pf = a.perf ? a.perf[q] : 1.0f;
-  const float4 cl = T->cls[lq & kClassMask];
-  const float B = (cl.x + cl.y) * pf;
   const size_t nb[6] = {q - sx, q + sx, q - sy, q + sy, q - 1, q + 1};
-  float diag = 1.0f - B;
-  float off = 0.0f;
+  float nlam[6];
+  unsigned nlab[6];
   for (int f = 0; f < 6; ++f) {
-    const unsigned lp = a.lab[nb[f]];
-    diag -= coef(T, f >> 1, lq, lp);                  // q's own row
-    if (!(lp & kHeld)) off = __builtin_fmaf(coef(T, f >> 1, lp, lq), a.lam_in[nb[f]], off);
+    nlam[f] = a.lam_in[nb[f]];
+    nlab[f] = a.lab[nb[f]];
   }
-  // damage-rate derivative at theta^n (zero where the exponent is capped)
-  float dr = 0.0f;
-  if (lq & kTissue) {
-    const float tk = K.tak + th;
-    const float x = K.c2 * th / tk;
-    if (x < K.clamp2) {
-      const float rate = K.dtka * __builtin_amdgcn_exp2f(x);
-      dr = rate * (K.c2 * 0.69314718f) * K.tak / (tk * tk);
+  float lo, sa = a.sacc[q], fa = a.facc[q];
+  adjoint_voxel(a.lam_in[q], a.theta[q], lq, a.perf ? a.perf[q] : 1.0f, a.w[q], nlam, nlab,
+                &a.tab->cf[0][0], a.tab->cls, K, lo, sa, fa);
+  a.lam_out[q] = lo;
+  a.sacc[q] = sa;
+  a.facc[q] = fa;
+}
+
+namespace {
+
+constexpr int kAdjAhead = 3;             // planes in flight ahead of the computed one
+constexpr int kAdjRing = kAdjAhead + 1;  // register ring (unroll factor)
+
+struct AdjPlane {
+  float lam;      // own lambda^{n+1}
+  unsigned b;     // own class byte
+  float hl;       // halo element lambda
+  unsigned hb;    // halo element class byte
+  float th, w, pf, sa, fa;
+};
+
+template <int TY>
+struct AdjSmem {
+  static constexpr int W = 66;
+  static constexpr int ROWS = TY + 2;
+  static constexpr int CELLS = ROWS * W;
+  float2 cf[3 * kMaxClasses * kMaxClasses];
+  float4 cls[kMaxClasses];
+  float lam[2][CELLS + 1];
+  uint8_t lab[2][CELLS + 1];
+};
+
+}  // namespace
+
+// Adjoint step with the production step kernel's schedule: a work-group of
+// TY waves owns a 64 (z) x TY (y) tile and marches along x; y and z
+// neighbours of lambda and the class byte come from a double-buffered LDS
+// plane with a one-voxel halo, x neighbours from registers, loads are
+// issued kAdjAhead planes ahead into a register ring, and stores that must
+// not happen (outside the grid, past the chunk, accumulators of held
+// voxels) get an out-of-range buffer offset instead of a branch.  The
+// per-voxel arithmetic is adjoint_voxel(), as in the reference kernel.
+template <int TY, bool PERF>
+__global__ __launch_bounds__(64 * TY) void k_adjoint_tiled(AdjointBuffers a, StepConst K,
+                                                           int nx, int ny, int nz, int xc,
+                                                           int tiles_z, int tiles_y, int nwg) {
+  using namespace tile;
+  constexpr int W = AdjSmem<TY>::W;
+  constexpr int CELLS = AdjSmem<TY>::CELLS;
+  __shared__ AdjSmem<TY> sm;
+  stage_tables(sm.cf, sm.cls, a.tab, kMaxClasses, 64 * TY);
+  const int wg = remap_xcd(blockIdx.x, nwg);
+  const int tz = wg % tiles_z;
+  const int ty = (wg / tiles_z) % tiles_y;
+  const int tx = wg / (tiles_z * tiles_y);
+  const int lane = threadIdx.x & 63;
+  const int wy = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int z = tz * 64 + lane;
+  const int y = ty * TY + wy;
+  const int x0 = tx * xc;
+  const int x1 = min(x0 + xc, nx);
+  const bool inside = z < nz && y < ny;
+  const int xb = max(x0 - 1, 0);
+  const unsigned psz = (unsigned)(ny * nz);
+  const unsigned col = inside ? (unsigned)(y * nz + z) : 0u;
+
+  __amdgpu_buffer_rsrc_t r_lam, r_lab, r_th, r_w, r_pf, r_sa, r_fa, r_out;
+  {
+    const size_t off = (size_t)xb * psz;
+    const size_t rest = (size_t)(nx - xb) * psz;
+    r_lam = make_rsrc(a.lam_in + off, rest * 4);
+    r_lab = make_rsrc(a.lab + off, rest);
+    r_th = make_rsrc(a.theta + off, rest * 4);
+    r_w = make_rsrc(a.w + off, rest * 4);
+    r_pf = make_rsrc(PERF ? a.perf + off : a.w + off, rest * 4);
+    r_sa = make_rsrc(a.sacc + off, rest * 4);
+    r_fa = make_rsrc(a.facc + off, rest * 4);
+    r_out = make_rsrc(a.lam_out + off, rest * 4);
+  }
+
+  // halo element of this thread (rows y0-1 / y0+TY, columns z0-1 / z0+64)
+  int hcell = CELLS, hy = -1, hz = -1;
+  {
+    const int y0 = ty * TY, z0 = tz * 64;
+    int hrow = 0, hcol = 0;
+    if (tid < 64) {
+      hrow = 0; hcol = tid + 1; hy = y0 - 1; hz = z0 + tid;
+    } else if (tid < 128) {
+      hrow = TY + 1; hcol = tid - 64 + 1; hy = y0 + TY; hz = z0 + tid - 64;
+    } else if (tid < 128 + TY) {
+      hrow = tid - 128 + 1; hcol = 0; hy = y0 + tid - 128; hz = z0 - 1;
+    } else if (tid < 128 + 2 * TY) {
+      hrow = tid - 128 - TY + 1; hcol = 65; hy = y0 + tid - 128 - TY; hz = z0 + 64;
     }
+    if (hy >= 0 && hy < ny && hz >= 0 && hz < nz) hcell = hrow * W + hcol;
   }
-  a.lam_out[q] = __builtin_fmaf(diag, lam, off) + a.w[q] * dr;
-  a.sacc[q] += lam;
-  a.facc[q] = __builtin_fmaf(-cl.x - cl.y, th * lam, a.facc[q]);
+  const unsigned hoff = hcell < CELLS ? (unsigned)(hy * nz + hz) : col;
+
+  auto load = [&](int x, AdjPlane& q) {
+    const int xo = min(x, nx - 1) - xb;  // uniform
+    const int xf = min(x, x1 - 1) - xb;  // uniform
+    const int so4 = xo * (int)psz * 4, so1 = xo * (int)psz;
+    const int sf4 = xf * (int)psz * 4, sf1 = xf * (int)psz;
+    q.lam = ld_f32(r_lam, col * 4, so4);
+    q.b = ld_u8(r_lab, col, so1);
+    q.hl = ld_f32(r_lam, hoff * 4, sf4);
+    q.hb = ld_u8(r_lab, hoff, sf1);
+    q.th = ld_f32(r_th, col * 4, sf4);
+    q.w = ld_f32(r_w, col * 4, sf4);
+    q.pf = PERF ? ld_f32(r_pf, col * 4, sf4) : 1.0f;
+    q.sa = ld_f32(r_sa, col * 4, sf4);
+    q.fa = ld_f32(r_fa, col * 4, sf4);
+  };
+
+  float lm;  // lambda of the x-1 neighbour (own column)
+  unsigned bm;
+  {
+    const int so = (max(x0 - 1, 0) - xb) * (int)psz;
+    lm = ld_f32(r_lam, col * 4, so * 4);
+    bm = ld_u8(r_lab, col, so);
+  }
+  AdjPlane q[kAdjRing];
+#pragma unroll
+  for (int k = 0; k < kAdjAhead; ++k) load(x0 + k, q[k]);
+  const int me = (wy + 1) * W + lane + 1;
+  const unsigned st4 = inside ? col * 4 : kOob;
+
+  auto plane = [&](auto S_, int x) {
+    constexpr int S = decltype(S_)::value;
+    constexpr int BUF = S & 1;
+    constexpr int SN = (S + 1) % kAdjRing;
+    constexpr int SA = (S + kAdjAhead) % kAdjRing;
+    load(x + kAdjAhead, q[SA]);
+    const AdjPlane& P = q[S];
+    sm.lam[BUF][me] = P.lam;
+    sm.lab[BUF][me] = (uint8_t)P.b;
+    sm.lam[BUF][hcell] = P.hl;
+    sm.lab[BUF][hcell] = (uint8_t)P.hb;
+    __syncthreads();
+    const AdjPlane& N = q[SN];
+    const float nlam[6] = {lm, N.lam, sm.lam[BUF][me - W], sm.lam[BUF][me + W],
+                           sm.lam[BUF][me - 1], sm.lam[BUF][me + 1]};
+    const unsigned nlab[6] = {bm, N.b, sm.lab[BUF][me - W], sm.lab[BUF][me + W],
+                              sm.lab[BUF][me - 1], sm.lab[BUF][me + 1]};
+    const bool valid = x < x1;  // uniform
+    float lo, sa = P.sa, fa = P.fa;
+    const bool free = adjoint_voxel(P.lam, P.th, P.b, P.pf, P.w, nlam, nlab, sm.cf, sm.cls, K,
+                                    lo, sa, fa);
+    const int so = (min(x, x1 - 1) - xb) * (int)psz * 4;  // uniform
+    const unsigned v = valid ? st4 : kOob;
+    st_f32(lo, r_out, v, so);
+    st_f32(sa, r_sa, free ? v : kOob, so);
+    st_f32(fa, r_fa, free ? v : kOob, so);
+    lm = P.lam;
+    bm = P.b;
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  static_assert(kAdjRing == 4, "unrolled for a ring of four planes");
+  for (int x = x0; x < x1; x += kAdjRing) {
+    plane(I0{}, x);
+    plane(I1{}, x + 1);
+    plane(I2{}, x + 2);
+    plane(I3{}, x + 3);
+  }
 }
 
 hipError_t launch_adjoint_step(Grid3 g, const AdjointBuffers& a, const StepConst& K,
                                hipStream_t st) {
   dim3 grid((g.nz + 63) / 64, (g.ny + 3) / 4, g.nx), block(64, 4);
   hipLaunchKernelGGL(k_adjoint_step, grid, block, 0, st, a, K, g.nx, g.ny, g.nz);
+  return hipGetLastError();
+}
+
+bool adjoint_tiled_fits(Grid3 g, int xc) {
+  return (double)(xc + kAdjAhead + 2) * g.ny * g.nz * 4.0 < 2147483647.0;
+}
+
+hipError_t launch_adjoint_tiled(Grid3 g, int ty, int xc, const AdjointBuffers& a,
+                                const StepConst& K, hipStream_t st) {
+  if (!adjoint_tiled_fits(g, xc)) return hipErrorInvalidValue;
+  const TiledShape s = tiled_shape(g, ty, xc);
+  const dim3 grid(s.nwg);
+  if (ty == 4) {
+    if (a.perf)
+      hipLaunchKernelGGL((k_adjoint_tiled<4, true>), grid, dim3(256), 0, st, a, K, g.nx, g.ny,
+                         g.nz, xc, s.tiles_z, s.tiles_y, s.nwg);
+    else
+      hipLaunchKernelGGL((k_adjoint_tiled<4, false>), grid, dim3(256), 0, st, a, K, g.nx, g.ny,
+                         g.nz, xc, s.tiles_z, s.tiles_y, s.nwg);
+  } else if (ty == 8) {
+    if (a.perf)
+      hipLaunchKernelGGL((k_adjoint_tiled<8, true>), grid, dim3(512), 0, st, a, K, g.nx, g.ny,
+                         g.nz, xc, s.tiles_z, s.tiles_y, s.nwg);
+    else
+      hipLaunchKernelGGL((k_adjoint_tiled<8, false>), grid, dim3(512), 0, st, a, K, g.nx, g.ny,
+                         g.nz, xc, s.tiles_z, s.tiles_y, s.nwg);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

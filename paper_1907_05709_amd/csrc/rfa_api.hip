@@ -1219,6 +1219,15 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
   HIP_TRY(hipMemcpyAsync(g->lab_scratch, g->lab, n, hipMemcpyDeviceToDevice, g->st));
   if ((s = prepare_dt(g, g->adj_dt)) != RFA_OK) return s;
   const StepConst K = step_const(g, g->adj_dt);
+  // adjoint schedule: the tiled kernel (4 rows, about 1024 work-groups)
+  // unless the grid asked for the reference kernels
+  int adj_xc = 4;
+  {
+    const int tiles = ((g->g.nz + 63) / 64) * ((g->g.ny + 3) / 4);
+    const int chunks = std::max(1, (1024 + tiles - 1) / tiles);
+    adj_xc = std::min(g->g.nx, std::max(4, (g->g.nx + chunks - 1) / chunks));
+  }
+  const bool tiled_adj = g->plan.kind != kStepNaive && adjoint_tiled_fits(g->g, adj_xc);
   int lc = 0;
   for (int seg = g->adj_nckpt - 1; seg >= 0; --seg) {
     const int k = std::min(every, g->adj_steps - seg * every);
@@ -1251,7 +1260,10 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
       a.tab = g->tab_dev;
       a.sacc = sacc;
       a.facc = facc;
-      HIP_TRY(launch_adjoint_step(g->g, a, K, g->st));
+      if (tiled_adj)
+        HIP_TRY(launch_adjoint_tiled(g->g, 4, adj_xc, a, K, g->st));
+      else
+        HIP_TRY(launch_adjoint_step(g->g, a, K, g->st));
       lc = 1 - lc;
     }
   }

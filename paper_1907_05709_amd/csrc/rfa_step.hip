@@ -8,7 +8,7 @@
 namespace rfa {
 
 namespace {
-constexpr int kTargetWg = 1536;  // ~6 work-groups per CU on 256 CUs
+constexpr int kTargetWg = 1024;  // ~4 work-groups per CU on 256 CUs
 }
 
 namespace {
@@ -21,10 +21,12 @@ StepPlan with_one(StepPlan p, const StepPlan& one) {
   return p;
 }
 
-// x chunk giving about `target` work-groups for `tiles` tiles per plane
+// x chunk giving about `target` work-groups for `tiles` tiles per plane,
+// rounded up to the kernels' four-plane unroll
 int default_xc(Grid3 g, int tiles, int target = kTargetWg) {
   const int chunks = std::max(1, (target + tiles - 1) / tiles);
-  return std::min(g.nx, std::max(4, (g.nx + chunks - 1) / chunks));
+  const int xc = (g.nx + chunks - 1) / chunks;
+  return std::min(g.nx, std::max(4, (xc + 3) / 4 * 4));
 }
 
 // Work-groups that fit the chip at once with the wide kernel (4-wave
@@ -109,7 +111,7 @@ StepPlan plan_default(Grid3 g, int kernel, int depth, int tile_y, int tile_x, in
     return plan_tiled2(g, ty, xc);
   }
   int ty = tile_y;
-  if (ty == 0) ty = g.ny >= 64 ? 8 : 4;
+  if (ty == 0) ty = g.ny >= 192 ? 8 : 4;
   const int tiles = ((g.nz + 63) / 64) * ((g.ny + ty - 1) / ty);
   int xc = tile_x ? std::min(tile_x, g.nx) : default_xc(g, tiles);
   while (xc > 4 && !tiled_fits(g, xc)) xc /= 2;
