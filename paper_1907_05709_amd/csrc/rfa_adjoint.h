@@ -20,10 +20,13 @@ struct AdjointBuffers {
 };
 
 hipError_t launch_bspline_eval(Grid3 g, const float* ctrl, int m, float* f, hipStream_t st);
-// vfirst_a[s] = first voxel of knot span s along axis a, s = 0 .. m-3.
+// gctrl[m^3] = sum_p gf_p f_p B(x_p) as three separable contractions (FP64,
+// fixed order).  vfirst_a[s] = first voxel of knot span s along axis a,
+// s = 0 .. m-3; scratch holds bspline_grad_scratch(g, m) doubles.
+size_t bspline_grad_scratch(Grid3 g, int m);
 hipError_t launch_bspline_grad(Grid3 g, const float* gf, const float* f, int m,
                                const int* vfirst_x, const int* vfirst_y, const int* vfirst_z,
-                               double* gctrl, hipStream_t st);
+                               double* scratch, double* gctrl, hipStream_t st);
 hipError_t launch_adjoint_weight(Grid3 g, const float* w, const float* om, const uint8_t* lab,
                                  float cap, float* wa, hipStream_t st);
 // Reference adjoint step (one thread per voxel).
@@ -39,5 +42,9 @@ hipError_t launch_source_dot(Grid3 g, double dx, double dy, double dz, const uin
                              const Chord* chords, const int* tine_first, int n_tines,
                              double sigma, const float* sacc, const ClassParams* cp_dev,
                              double dt, double* partial, int nblk, hipStream_t st);
+
+hipError_t launch_source_dot_fields(Grid3 g, const uint8_t* lab, const double* u, int n_tines,
+                                    const float* sacc, const ClassParams* cp_dev, double dt,
+                                    double* partial, int nblk, hipStream_t st);
 
 }  // namespace rfa

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "rfa_adjoint.h"
 #include "rfa_tile_common.h"
 #include "rfa_tiled.h"
@@ -97,55 +99,61 @@ hipError_t launch_bspline_eval(Grid3 g, const float* ctrl, int m, float* f, hipS
   return hipGetLastError();
 }
 
-// gctrl[j] = sum_p gf_p f_p B_j(x_p): one block per control point gathers
-// over the voxels of its support box (fixed order, deterministic).
-__global__ __launch_bounds__(256) void k_bspline_grad(const float* gf, const float* f, int m,
-                                                      int nx, int ny, int nz,
-                                                      const int* vfirst_x,
-                                                      const int* vfirst_y,
-                                                      const int* vfirst_z, double* gctrl) {
-  __shared__ double sh[4];
-  const int j = blockIdx.x;
-  const int ja = j / (m * m), jb = (j / m) % m, jc = j % m;
-  // voxels whose span s satisfies s <= j <= s + 3, i.e. s in [j-3, j]
-  auto range = [&](int jj, const int* vf, int& lo, int& hi) {
-    const int s0 = jj - 3 < 0 ? 0 : jj - 3;
-    const int s1 = jj > m - 4 ? m - 4 : jj;
-    lo = vf[s0];
-    hi = vf[s1 + 1];
-  };
-  int x0, x1, y0, y1, z0, z1;
-  range(ja, vfirst_x, x0, x1);
-  range(jb, vfirst_y, y0, y1);
-  range(jc, vfirst_z, z0, z1);
-  const int ex = x1 - x0, ey = y1 - y0, ez = z1 - z0;
-  const long long cnt = (long long)ex * ey * ez;
-  double acc = 0.0;
-  for (long long e = threadIdx.x; e < cnt; e += 256) {
-    const int k = z0 + (int)(e % ez), jy = y0 + (int)((e / ez) % ey), i = x0 + (int)(e / ((long long)ez * ey));
-    int si, sj, sk;
-    double ti, tj, tk, bi[4], bj[4], bk[4];
-    span_of(i, nx, m, si, ti);
-    span_of(jy, ny, m, sj, tj);
-    span_of(k, nz, m, sk, tk);
-    const int a = ja - si, b = jb - sj, c = jc - sk;
-    if (a < 0 || a > 3 || b < 0 || b > 3 || c < 0 || c > 3) continue;
-    basis(ti, bi);
-    basis(tj, bj);
-    basis(tk, bk);
-    const size_t p = ((size_t)i * ny + jy) * nz + k;
-    acc += (double)gf[p] * (double)f[p] * bi[a] * bj[b] * bk[c];
+// One factor of the separable B-spline transpose: contract the middle axis
+// (n voxels) of a [N0][n][N2] array against the m basis functions of that
+// axis, out[o0][c][o2] = sum_{i in support(c)} in[o0][i][o2] B_c(i), summed
+// in increasing i.  vfirst[s] = first voxel of knot span s (s = 0 .. m-3).
+// With in == nullptr the input is gf * f (FP64 products of the two fields).
+__global__ __launch_bounds__(256) void k_bspline_contract(const double* in, const float* gf,
+                                                          const float* f, long long N0, int n,
+                                                          int N2, int m, const int* vfirst,
+                                                          double* out) {
+  const long long total = N0 * m * N2;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int o2 = (int)(e % N2);
+    const long long r = e / N2;
+    const int c = (int)(r % m);
+    const long long o0 = r / m;
+    const int s0 = c - 3 < 0 ? 0 : c - 3;
+    const int s1 = c > m - 4 ? m - 4 : c;
+    const int lo = vfirst[s0], hi = vfirst[s1 + 1];
+    double acc = 0.0;
+    for (int i = lo; i < hi; ++i) {
+      int sp;
+      double t, bb[4];
+      span_of(i, n, m, sp, t);
+      basis(t, bb);
+      const size_t idx = ((size_t)o0 * n + i) * N2 + o2;
+      const double v = in ? in[idx] : (double)gf[idx] * (double)f[idx];
+      acc += v * bb[c - sp];
+    }
+    out[e] = acc;
   }
-  acc = block_sum_256(acc, sh);
-  if (threadIdx.x == 0) gctrl[j] = acc;
 }
 
 hipError_t launch_bspline_grad(Grid3 g, const float* gf, const float* f, int m,
                                const int* vfirst_x, const int* vfirst_y, const int* vfirst_z,
-                               double* gctrl, hipStream_t st) {
-  hipLaunchKernelGGL(k_bspline_grad, dim3(m * m * m), dim3(256), 0, st, gf, f, m, g.nx, g.ny,
-                     g.nz, vfirst_x, vfirst_y, vfirst_z, gctrl);
+                               double* scratch, double* gctrl, hipStream_t st) {
+  // gctrl[a][b][c] = sum_p gf_p f_p Bx_a(i) By_b(j) Bz_c(k): z, then y, then x
+  double* t1 = scratch;                               // [nx][ny][m]
+  double* t2 = scratch + (size_t)g.nx * g.ny * m;     // [nx][m][m]
+  auto blocks = [](long long total) {
+    return (unsigned)std::min<long long>((total + 255) / 256, 8192);
+  };
+  const long long n1 = (long long)g.nx * g.ny * m, n2 = (long long)g.nx * m * m,
+                  n3 = (long long)m * m * m;
+  hipLaunchKernelGGL(k_bspline_contract, dim3(blocks(n1)), dim3(256), 0, st, nullptr, gf, f,
+                     (long long)g.nx * g.ny, g.nz, 1, m, vfirst_z, t1);
+  hipLaunchKernelGGL(k_bspline_contract, dim3(blocks(n2)), dim3(256), 0, st, t1, nullptr,
+                     nullptr, (long long)g.nx, g.ny, m, m, vfirst_y, t2);
+  hipLaunchKernelGGL(k_bspline_contract, dim3(blocks(n3)), dim3(256), 0, st, t2, nullptr,
+                     nullptr, 1LL, g.nx, m * m, m, vfirst_x, gctrl);
   return hipGetLastError();
+}
+
+size_t bspline_grad_scratch(Grid3 g, int m) {
+  return (size_t)g.nx * g.ny * m + (size_t)g.nx * m * m;
 }
 
 // w' = w on tissue voxels whose damage integral stayed below the cap, else 0.
@@ -462,6 +470,36 @@ __global__ __launch_bounds__(256) void k_source_dot(const uint8_t* lab, const Ch
   }
   acc = block_sum_256(acc, sh);
   if (threadIdx.x == 0) partial[(size_t)t * gridDim.x + blockIdx.x] = acc;
+}
+
+// The same sums from stored per-tine densities u[t][n] (same traversal and
+// order, so identical results).
+__global__ __launch_bounds__(256) void k_source_dot_fields(const uint8_t* lab, const double* u,
+                                                           const float* sacc,
+                                                           const ClassParams* cp, double dt,
+                                                           size_t n, double* partial) {
+  __shared__ double sh[4];
+  const int t = blockIdx.y;
+  const double* ut = u + (size_t)t * n;
+  double acc = 0.0;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (size_t)gridDim.x * blockDim.x) {
+    const unsigned v = lab[p];
+    if (v & kHeld) continue;
+    const double sv = (double)sacc[p] * dt / cp->rc[v & kClassMask];
+    if (sv == 0.0) continue;
+    acc += ut[p] * sv;
+  }
+  acc = block_sum_256(acc, sh);
+  if (threadIdx.x == 0) partial[(size_t)t * gridDim.x + blockIdx.x] = acc;
+}
+
+hipError_t launch_source_dot_fields(Grid3 g, const uint8_t* lab, const double* u, int n_tines,
+                                    const float* sacc, const ClassParams* cp_dev, double dt,
+                                    double* partial, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_source_dot_fields, dim3(nblk, n_tines), dim3(256), 0, st, lab, u, sacc,
+                     cp_dev, dt, g.n(), partial);
+  return hipGetLastError();
 }
 
 hipError_t launch_source_dot(Grid3 g, double dx, double dy, double dz, const uint8_t* lab,

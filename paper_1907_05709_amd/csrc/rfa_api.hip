@@ -44,6 +44,7 @@ rfa_status fail(rfa_status s, const char* fmt, ...) {
   } while (0)
 
 constexpr int kPartialSlots = 64;  // steps of diagnostic partials per reduction
+constexpr size_t kFieldBudget = size_t(16) << 30;  // bytes of kept per-tine source densities
 constexpr int kTimedBatch = 1024;  // launches between event read-backs
 constexpr double kTBodyK = 310.15;
 constexpr double kExponentClamp = 80.0;
@@ -85,6 +86,11 @@ struct rfa_grid_s {
   Chord* chords_dev = nullptr;     // chords of the rasterised needle
   int* first_dev = nullptr;        // first chord of each tine (+ end)
   std::vector<double> tine_sums;   // integral of each tine's unnormalised density, m
+  double* tine_u = nullptr;        // [n_tines][n] unnormalised densities (if kept)
+  size_t tine_u_cap = 0;           // doubles allocated at tine_u
+  bool fields_ok = false;          // tine_u holds the current needle's densities
+  double* scale_dev = nullptr;     // [scale_cap] power / integral per tine
+  size_t scale_cap = 0;
 
   // perfusion-correction B-spline (m^3 control points), if set
   int bs_m = 0;
@@ -154,6 +160,8 @@ void free_all(rfa_grid g) {
   f(g->bad);
   f(g->chords_dev);
   f(g->first_dev);
+  f(g->tine_u);
+  f(g->scale_dev);
   f(g->bs_ctrl);
   f(g->bs_vfirst);
   f(g->ckpt);
@@ -245,6 +253,7 @@ rfa_status compute_dt_max(rfa_grid g) {
 rfa_status rasterise(rfa_grid g) {
   g->src_dt = -1.0;
   ++g->version;
+  g->fields_ok = false;
   if (!g->has_needle) {
     HIP_TRY(hipMemsetAsync(g->q64, 0, g->g.n() * sizeof(double), g->st));
     g->rf_power = 0.0;
@@ -297,13 +306,36 @@ rfa_status rasterise(rfa_grid g) {
   std::vector<double> sums(nt), scale(nt);
   hipError_t e = hipSuccess;
   int nblk = 0;
+  // Keep the per-tine densities when they fit the budget: new tine powers
+  // then only recombine them, and dL/dP reads them instead of recomputing.
+  const size_t nu = (size_t)nt * g->g.n();
+  bool keep = nu * sizeof(double) <= kFieldBudget;
+  if (keep && g->tine_u_cap < nu) {
+    if (g->tine_u) (void)hipFree(g->tine_u);
+    g->tine_u = nullptr;
+    g->tine_u_cap = 0;
+    if (hipMalloc((void**)&g->tine_u, nu * sizeof(double)) == hipSuccess)
+      g->tine_u_cap = nu;
+    else
+      keep = false;  // fall back to recomputing the densities
+    (void)hipGetLastError();
+  }
+  g->fields_ok = false;
   do {
     if ((e = hipMemcpyAsync(d_chords, chords.data(), chords.size() * sizeof(Chord),
                             hipMemcpyHostToDevice, g->st)) != hipSuccess) break;
     if ((e = hipMemcpyAsync(d_first, first.data(), first.size() * sizeof(int),
                             hipMemcpyHostToDevice, g->st)) != hipSuccess) break;
-    if ((e = launch_source_sums(g->g, g->dx, g->dy, g->dz, g->lab, d_chords, d_first, nt,
-                                g->sigma, d_partial, &nblk, d_sums, g->st)) != hipSuccess) break;
+    if (keep) {
+      if ((e = launch_source_fields(g->g, g->dx, g->dy, g->dz, g->lab, d_chords, d_first, nt,
+                                    g->sigma, g->tine_u, g->st)) != hipSuccess) break;
+      if ((e = launch_field_sums(g->g, g->dx, g->dy, g->dz, g->lab, g->tine_u, nt, d_partial,
+                                 d_sums, g->st)) != hipSuccess) break;
+    } else if ((e = launch_source_sums(g->g, g->dx, g->dy, g->dz, g->lab, d_chords, d_first,
+                                       nt, g->sigma, d_partial, &nblk, d_sums, g->st)) !=
+               hipSuccess) {
+      break;
+    }
     if ((e = hipMemcpyAsync(sums.data(), d_sums, nt * sizeof(double), hipMemcpyDeviceToHost,
                             g->st)) != hipSuccess) break;
     if ((e = hipStreamSynchronize(g->st)) != hipSuccess) break;
@@ -322,14 +354,19 @@ rfa_status rasterise(rfa_grid g) {
   do {
     if ((e = hipMemcpyAsync(d_sums + nt, scale.data(), nt * sizeof(double),
                             hipMemcpyHostToDevice, g->st)) != hipSuccess) break;
-    if ((e = launch_source_write(g->g, g->dx, g->dy, g->dz, g->lab, d_chords, d_first, nt,
-                                 g->sigma, d_sums + nt, g->q64, g->st)) != hipSuccess) break;
+    if (keep)
+      e = launch_source_combine(g->g, g->lab, g->tine_u, nt, d_sums + nt, g->q64, g->st);
+    else
+      e = launch_source_write(g->g, g->dx, g->dy, g->dz, g->lab, d_chords, d_first, nt,
+                              g->sigma, d_sums + nt, g->q64, g->st);
+    if (e != hipSuccess) break;
     if ((e = hipStreamSynchronize(g->st)) != hipSuccess) break;
   } while (false);
   if (e != hipSuccess) {
     cleanup();
     return fail(RFA_ERR_HIP, "source write failed: %s", hipGetErrorString(e));
   }
+  g->fields_ok = keep;
   // keep the chord list and tine integrals for the adjoint's dL/dP
   (void)hipFree(d_sums);
   (void)hipFree(d_partial);
@@ -1134,6 +1171,30 @@ rfa_status rfa_set_tine_powers(rfa_grid g, const double* power) {
   for (size_t t = 0; t < nt; ++t)
     if (!(power[t] >= 0.0) || !std::isfinite(power[t]))
       return fail(RFA_ERR_ARG, "power of tine %zu must be finite and >= 0", t);
+  if (g->fields_ok) {
+    // recombine the kept per-tine densities with the new powers
+    std::vector<double> scale(nt);
+    for (size_t t = 0; t < nt; ++t) scale[t] = power[t] / g->tine_sums[t];
+    rfa_status s;
+    if (g->scale_cap < nt) {
+      if (g->scale_dev) (void)hipFree(g->scale_dev);
+      g->scale_dev = nullptr;
+      g->scale_cap = 0;
+      if ((s = dmalloc(&g->scale_dev, nt)) != RFA_OK) return s;
+      g->scale_cap = nt;
+    }
+    HIP_TRY(hipMemcpyAsync(g->scale_dev, scale.data(), nt * sizeof(double),
+                           hipMemcpyHostToDevice, g->st));
+    HIP_TRY(launch_source_combine(g->g, g->lab, g->tine_u, (int)nt, g->scale_dev, g->q64, g->st));
+    HIP_TRY(hipStreamSynchronize(g->st));
+    g->power.assign(power, power + nt);
+    g->src_dt = -1.0;
+    ++g->version;
+    double tot = 0.0;
+    for (double p : g->power) tot += p;
+    g->rf_power = tot;
+    return RFA_OK;
+  }
   std::vector<double> old = g->power;
   g->power.assign(power, power + nt);
   rfa_status s = rasterise(g);
@@ -1273,9 +1334,12 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
     double* part = nullptr;
     if ((s = dmalloc(&part, (size_t)nt * kBlk)) != RFA_OK) return s;
     std::vector<double> host((size_t)nt * kBlk);
-    hipError_t e = launch_source_dot(g->g, g->dx, g->dy, g->dz, g->lab, g->chords_dev,
-                                     g->first_dev, nt, g->sigma, sacc, g->cp_dev, g->adj_dt,
-                                     part, kBlk, g->st);
+    hipError_t e = g->fields_ok
+                       ? launch_source_dot_fields(g->g, g->lab, g->tine_u, nt, sacc, g->cp_dev,
+                                                  g->adj_dt, part, kBlk, g->st)
+                       : launch_source_dot(g->g, g->dx, g->dy, g->dz, g->lab, g->chords_dev,
+                                           g->first_dev, nt, g->sigma, sacc, g->cp_dev,
+                                           g->adj_dt, part, kBlk, g->st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(host.data(), part, host.size() * sizeof(double), hipMemcpyDeviceToHost,
                          g->st);
@@ -1294,10 +1358,10 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
     const int m = g->bs_m;
     const size_t nc = (size_t)m * m * m;
     double* gc = nullptr;
-    if ((s = dmalloc(&gc, nc)) != RFA_OK) return s;
+    if ((s = dmalloc(&gc, nc + bspline_grad_scratch(g->g, m))) != RFA_OK) return s;
     hipError_t e = launch_bspline_grad(g->g, facc, g->perf, m, g->bs_vfirst,
-                                       g->bs_vfirst + (m - 2), g->bs_vfirst + 2 * (m - 2), gc,
-                                       g->st);
+                                       g->bs_vfirst + (m - 2), g->bs_vfirst + 2 * (m - 2),
+                                       gc + nc, gc, g->st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(dL_dctrl, gc, nc * sizeof(double), hipMemcpyDeviceToHost, g->st);
     if (e == hipSuccess) e = hipStreamSynchronize(g->st);

@@ -105,6 +105,16 @@ hipError_t launch_source_write(Grid3 g, double dx, double dy, double dz, const u
                                const Chord* chords, const int* tine_first, int n_tines,
                                double sigma, const double* scale, double* q,
                                hipStream_t st);
+// Stored per-tine densities u[t][n] (0 on held voxels), their integrals
+// (same order as launch_source_sums) and q = sum_t scale[t] u_t.
+hipError_t launch_source_fields(Grid3 g, double dx, double dy, double dz, const uint8_t* lab,
+                                const Chord* chords, const int* tine_first, int n_tines,
+                                double sigma, double* u, hipStream_t st);
+hipError_t launch_field_sums(Grid3 g, double dx, double dy, double dz, const uint8_t* lab,
+                             const double* u, int n_tines, double* partial, double* sums,
+                             hipStream_t st);
+hipError_t launch_source_combine(Grid3 g, const uint8_t* lab, const double* u, int n_tines,
+                                 const double* scale, double* q, hipStream_t st);
 // s = dt q / (rho c) on free voxels, 0 on held voxels.
 hipError_t launch_source_increment(Grid3 g, const uint8_t* lab, const double* q,
                                    const ClassParams* cp_dev, double dt, float* s,

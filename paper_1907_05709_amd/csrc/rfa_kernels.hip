@@ -396,6 +396,83 @@ hipError_t launch_source_sums(Grid3 g, double dx, double dy, double dz, const ui
   return hipGetLastError();
 }
 
+// u[t][p] = g_t(p), the unnormalised density of tine t, on free voxels and
+// 0 on held ones (kept so that new tine powers only recombine the fields).
+__global__ void k_source_fields(const uint8_t* lab, const Chord* chords, const int* tine_first,
+                                int n_tines, double sigma, double* u, int nx, int ny, int nz,
+                                double dx, double dy, double dz) {
+  const size_t n = (size_t)nx * ny * nz;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (size_t)gridDim.x * blockDim.x) {
+    if (lab[p] & kHeld) {
+      for (int t = 0; t < n_tines; ++t) u[(size_t)t * n + p] = 0.0;
+      continue;
+    }
+    const int k = (int)(p % nz);
+    const int j = (int)((p / nz) % ny);
+    const int i = (int)(p / ((size_t)nz * ny));
+    const double x = (2.0 * i - (nx - 1)) * dx / 2.0;
+    const double y = (2.0 * j - (ny - 1)) * dy / 2.0;
+    const double z = (2.0 * k - (nz - 1)) * dz / 2.0;
+    for (int t = 0; t < n_tines; ++t)
+      u[(size_t)t * n + p] = tine_density(chords, tine_first[t], tine_first[t + 1], x, y, z, sigma);
+  }
+}
+
+// Per-tine integrals from stored fields: the traversal and summation order
+// of k_source_sums, so the results are identical.
+__global__ __launch_bounds__(kRedThreads) void k_field_sums(const uint8_t* lab, const double* u,
+                                                            size_t n, double* partial) {
+  __shared__ double sh[kRedThreads / 64];
+  const int t = blockIdx.y;
+  const double* ut = u + (size_t)t * n;
+  double acc = 0.0;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (size_t)gridDim.x * blockDim.x) {
+    if (lab[p] & kHeld) continue;
+    acc += ut[p];
+  }
+  acc = block_sum_d(acc, sh);
+  if (threadIdx.x == 0) partial[(size_t)t * gridDim.x + blockIdx.x] = acc;
+}
+
+// q[p] = sum_t scale[t] u_t(p) on free voxels, in the order of k_source_write.
+__global__ void k_source_combine(const uint8_t* lab, const double* u, int n_tines,
+                                 const double* scale, double* q, size_t n) {
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (size_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    if (!(lab[p] & kHeld))
+      for (int t = 0; t < n_tines; ++t) v += scale[t] * u[(size_t)t * n + p];
+    q[p] = v;
+  }
+}
+
+hipError_t launch_source_fields(Grid3 g, double dx, double dy, double dz, const uint8_t* lab,
+                                const Chord* chords, const int* tine_first, int n_tines,
+                                double sigma, double* u, hipStream_t st) {
+  hipLaunchKernelGGL(k_source_fields, dim3(4096), dim3(256), 0, st, lab, chords, tine_first,
+                     n_tines, sigma, u, g.nx, g.ny, g.nz, dx, dy, dz);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_sums(Grid3 g, double dx, double dy, double dz, const uint8_t* lab,
+                             const double* u, int n_tines, double* partial, double* sums,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_field_sums, dim3(kRedBlocks, n_tines), dim3(kRedThreads), 0, st, lab, u,
+                     g.n(), partial);
+  hipLaunchKernelGGL(k_sum_rows, dim3(n_tines), dim3(kRedThreads), 0, st, partial, kRedBlocks,
+                     dx * dy * dz, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_source_combine(Grid3 g, const uint8_t* lab, const double* u, int n_tines,
+                                 const double* scale, double* q, hipStream_t st) {
+  hipLaunchKernelGGL(k_source_combine, dim3(4096), dim3(256), 0, st, lab, u, n_tines, scale, q,
+                     g.n());
+  return hipGetLastError();
+}
+
 // q[p] = sum_t scale[t] * g_t(p) on free voxels (scale = power / integral).
 __global__ void k_source_write(const uint8_t* lab, const Chord* chords, const int* tine_first,
                                int n_tines, double sigma, const double* scale, double* q, int nx,

@@ -288,6 +288,28 @@ def test_two_step_kernel_matches_oracle_on_the_straight_recipe():
     g.close()
 
 
+def test_new_tine_powers_equal_a_fresh_needle():
+    """New tine powers recombine the kept per-tine source densities; the
+    result must be bitwise that of rasterising the needle with those powers."""
+    import copy
+    from paper_1907_05709_amd import rfa
+    case = W.random_tissue_case(55, shape=(30, 26, 34), n_classes=4, n_tines=3, n_steps=25)
+    P2 = np.array([3.0, 0.0, 7.5]) * case.needle.power.mean()
+    fresh = copy.deepcopy(case)
+    fresh.needle.power = P2.copy()
+    g1, g2 = rfa.Grid(case.shape, case.spacing), rfa.Grid(case.shape, case.spacing)
+    g1.load_case(case)
+    g1.set_tine_powers(P2)
+    g2.load_case(fresh)
+    dt = 0.9 * min(case.dt, g1.dt_max())
+    for g in (g1, g2):
+        g.step(25, dt, diag=False)
+    assert np.array_equal(g1.temperature(), g2.temperature())
+    assert np.abs(g1.temperature() - 37.0).max() > 1e-3
+    g1.close()
+    g2.close()
+
+
 def test_tune_keeps_state_and_timing_counts_launches():
     from paper_1907_05709_amd import rfa
     case = W.case_straight(n=48, n_steps=20, seed=2005)
