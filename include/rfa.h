@@ -257,10 +257,14 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
 
 /* ---- Batched stepping of many grids (planning sweeps) ---------------------
  * A batch advances n independent grids -- each with its own shape, spacing,
- * tissue, needle and time step -- in lockstep: one step of all grids is one
- * kernel launch over the concatenated tile lists (two when some grids carry
- * a perfusion field and others do not), and the whole step loop of an rfa_batch_step call is captured once in a hipGraph
- * and replayed on later calls with the same step count.  The per-voxel
+ * tissue, needle and time step -- by the same number of steps.  Consecutive
+ * grids are grouped up to a voxel budget (by default 8 Mi voxels, whose
+ * stepping working set fits the 256 MB last-level cache); a group runs
+ * all its steps before the next group starts, one kernel launch per step
+ * over the concatenated tile lists of its grids (two when some grids carry a
+ * perfusion field and others do not).  The whole launch sequence of an
+ * rfa_batch_step call is captured once in a hipGraph and replayed on later
+ * calls with the same step count.  The per-voxel
  * arithmetic is that of rfa_step (Eq. (CUDAbioheat3d), Alg. 1 and 2), so a
  * batch step leaves each grid bitwise in the state rfa_step would.
  *
@@ -281,13 +285,16 @@ rfa_status rfa_batch_step(rfa_batch b, int n_steps, rfa_diag* diags);
 /* Launch shape of the batch kernel: tile_y (4 or 8) rows per work-group,
  * tile_x planes per work item, workgroups > 0 persistent work-groups per
  * launch that walk the work list (0, the default: one work-group per work
- * item).  Zero tile values keep the automatic choice.  Drops cached graphs. */
-rfa_status rfa_batch_set_plan(rfa_batch b, int tile_y, int tile_x, int workgroups);
+ * item), group_voxels the grouping budget (0: all grids in one group, i.e.
+ * lockstep; < 0: keep the current one).  Zero tile values keep the
+ * automatic choice.  Drops cached graphs. */
+rfa_status rfa_batch_set_plan(rfa_batch b, int tile_y, int tile_x, int workgroups,
+                              long long group_voxels);
 
-/* Current launch shape: tile_y, tile_x, work items per step, work-groups
- * launched per step. */
+/* Current launch shape: tile_y, tile_x, work items per step (all groups),
+ * work-groups launched per step of all grids, number of groups. */
 rfa_status rfa_batch_get_plan(rfa_batch b, int* tile_y, int* tile_x, int* items,
-                              int* workgroups);
+                              int* workgroups, int* groups);
 
 /* Device time of the last rfa_batch_step's graph, milliseconds (HIP events
  * on the batch's stream), and voxel-steps it advanced. */

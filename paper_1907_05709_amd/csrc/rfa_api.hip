@@ -45,6 +45,10 @@ rfa_status fail(rfa_status s, const char* fmt, ...) {
 
 constexpr int kPartialSlots = 64;  // steps of diagnostic partials per reduction
 constexpr size_t kFieldBudget = size_t(16) << 30;  // bytes of kept per-tine source densities
+// Voxels per batch group: a group's stepping working set (two state images,
+// class bytes, source, damage: ~29 B per voxel, 8 Mi voxels ~ 243 MB) stays
+// within the 256 MB last-level cache while its steps run.
+constexpr long long kBatchGroupVoxels = 8ll << 20;
 constexpr int kTimedBatch = 1024;  // launches between event read-backs
 constexpr double kTBodyK = 310.15;
 constexpr double kExponentClamp = 80.0;
@@ -1387,10 +1391,16 @@ struct rfa_batch_s {
   double* dacc = nullptr;           // [n][3]
   int n_items = 0;
   int ty = 4;
-  int xc = 16;
+  int xc = 8;
   int n_wg = 0;
   int req_wg = 0;                   // persistent work-groups (0: one per item)
-  int n_plain = 0;                  // items of grids without a perfusion field
+  long long group_budget = kBatchGroupVoxels;  // voxels per group (0: one group)
+  struct Group {
+    int inst0, inst1;               // instances [inst0, inst1)
+    int plain0, plain1;             // items of its grids without a perfusion field
+    int perf0, perf1;               // items of its grids with one
+  };
+  std::vector<Group> groups;
   int parity = 0;
   long long voxels = 0;
   hipStream_t st = nullptr;
@@ -1462,21 +1472,36 @@ rfa_status batch_build(rfa_batch b) {
     if (!tiled_fits(g->g, I.xc)) return fail(RFA_ERR_ARG, "grid %d too large for a batch", i);
     b->voxels += (long long)g->g.n();
   }
-  // work items: grids without a perfusion field first, then those with one
-  // (two kernel variants); each grid's items are contiguous
-  b->n_plain = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int i = 0; i < n; ++i) {
-      const BatchInstance& I = b->inst[i];
-      if ((I.perf != nullptr) != (pass == 1)) continue;
-      const TiledShape sh = tiled_shape(b->grids[i]->g, b->ty, I.xc);
-      b->first[2 * i] = (int)items.size();
-      for (int tx = 0; tx < sh.chunks_x; ++tx)
-        for (int ty = 0; ty < sh.tiles_y; ++ty)
-          for (int tz = 0; tz < sh.tiles_z; ++tz) items.push_back(BatchItem{i, tz, ty, tx});
-      b->first[2 * i + 1] = (int)items.size();
+  // Groups of consecutive grids up to the voxel budget; a group runs all its
+  // steps before the next starts (the grids are independent), so its
+  // working set stays in the last-level cache.  Work items of a group:
+  // grids without a perfusion field first, then those with one (two kernel
+  // variants); each grid's items are contiguous.
+  b->groups.clear();
+  for (int i0 = 0; i0 < n;) {
+    int i1 = i0 + 1;
+    long long vox = (long long)b->grids[i0]->g.n();
+    while (i1 < n && b->group_budget > 0 &&
+           vox + (long long)b->grids[i1]->g.n() <= b->group_budget)
+      vox += (long long)b->grids[i1++]->g.n();
+    if (b->group_budget == 0) i1 = n;
+    rfa_batch_s::Group G{i0, i1, 0, 0, 0, 0};
+    for (int pass = 0; pass < 2; ++pass) {
+      (pass == 0 ? G.plain0 : G.perf0) = (int)items.size();
+      for (int i = i0; i < i1; ++i) {
+        const BatchInstance& I = b->inst[i];
+        if ((I.perf != nullptr) != (pass == 1)) continue;
+        const TiledShape sh = tiled_shape(b->grids[i]->g, b->ty, I.xc);
+        b->first[2 * i] = (int)items.size();
+        for (int tx = 0; tx < sh.chunks_x; ++tx)
+          for (int ty = 0; ty < sh.tiles_y; ++ty)
+            for (int tz = 0; tz < sh.tiles_z; ++tz) items.push_back(BatchItem{i, tz, ty, tx});
+        b->first[2 * i + 1] = (int)items.size();
+      }
+      (pass == 0 ? G.plain1 : G.perf1) = (int)items.size();
     }
-    if (pass == 0) b->n_plain = (int)items.size();
+    b->groups.push_back(G);
+    i0 = i1;
   }
   b->n_items = (int)items.size();
   rfa_status s;
@@ -1525,27 +1550,30 @@ rfa_status batch_graph(rfa_batch b, int n_steps, bool diag, hipGraphExec_t* out)
   }
   HIP_TRY(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  int pending = 0;
-  for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
-    float* part = diag ? b->partials + (size_t)pending * b->n_items * 3 : nullptr;
-    const int par = (b->parity + s) & 1;
-    const int n_perf = b->n_items - b->n_plain;
-    const int wg_plain = b->n_wg > 0 ? std::min(b->n_wg, b->n_plain) : 0;
+  for (const auto& G : b->groups) {
+    // every step of this group's grids, then the next group
+    const int n_plain = G.plain1 - G.plain0, n_perf = G.perf1 - G.perf0;
+    const int wg_plain = b->n_wg > 0 ? std::min(b->n_wg, n_plain) : 0;
     const int wg_perf = b->n_wg > 0 ? std::min(b->n_wg, n_perf) : 0;
-    e = launch_step_batch(b->ty, false, b->inst_dev, b->items_dev, 0, b->n_plain, wg_plain,
-                          par, part, b->st);
-    if (e == hipSuccess)
-      e = launch_step_batch(b->ty, true, b->inst_dev, b->items_dev, b->n_plain, n_perf,
-                            wg_perf, par, part, b->st);
-    if (e == hipSuccess && diag && ++pending == kPartialSlots) {
-      e = launch_reduce_batch(b->partials, pending, b->n_items, b->first_dev,
-                              (int)b->grids.size(), b->dacc, b->st);
-      pending = 0;
+    int pending = 0;
+    for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
+      float* part = diag ? b->partials + (size_t)pending * b->n_items * 3 : nullptr;
+      const int par = (b->parity + s) & 1;
+      e = launch_step_batch(b->ty, false, b->inst_dev, b->items_dev, G.plain0, n_plain,
+                            wg_plain, par, part, b->st);
+      if (e == hipSuccess)
+        e = launch_step_batch(b->ty, true, b->inst_dev, b->items_dev, G.perf0, n_perf, wg_perf,
+                              par, part, b->st);
+      if (e == hipSuccess && diag && ++pending == kPartialSlots) {
+        e = launch_reduce_batch(b->partials, pending, b->n_items, b->first_dev, G.inst0,
+                                G.inst1 - G.inst0, b->dacc, b->st);
+        pending = 0;
+      }
     }
+    if (e == hipSuccess && diag && pending > 0)
+      e = launch_reduce_batch(b->partials, pending, b->n_items, b->first_dev, G.inst0,
+                              G.inst1 - G.inst0, b->dacc, b->st);
   }
-  if (e == hipSuccess && diag && pending > 0)
-    e = launch_reduce_batch(b->partials, pending, b->n_items, b->first_dev,
-                            (int)b->grids.size(), b->dacc, b->st);
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->st, &graph);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -1659,7 +1687,8 @@ rfa_status rfa_batch_step(rfa_batch b, int n_steps, rfa_diag* diags) {
   return RFA_OK;
 }
 
-rfa_status rfa_batch_set_plan(rfa_batch b, int tile_y, int tile_x, int workgroups) {
+rfa_status rfa_batch_set_plan(rfa_batch b, int tile_y, int tile_x, int workgroups,
+                              long long group_voxels) {
   if (!b) return fail(RFA_ERR_ARG, "batch is NULL");
   if (tile_y != 0 && tile_y != 4 && tile_y != 8) return fail(RFA_ERR_ARG, "tile_y: 0, 4 or 8");
   if (tile_x < 0 || workgroups < 0) return fail(RFA_ERR_ARG, "tile_x, workgroups >= 0");
@@ -1667,20 +1696,25 @@ rfa_status rfa_batch_set_plan(rfa_batch b, int tile_y, int tile_x, int workgroup
   if (tile_y) b->ty = tile_y;
   if (tile_x) b->xc = tile_x;
   b->req_wg = workgroups;
+  if (group_voxels >= 0) b->group_budget = group_voxels;
   return batch_build(b);
 }
 
 rfa_status rfa_batch_get_plan(rfa_batch b, int* tile_y, int* tile_x, int* items,
-                              int* workgroups) {
+                              int* workgroups, int* groups) {
   if (!b) return fail(RFA_ERR_ARG, "batch is NULL");
   if (tile_y) *tile_y = b->ty;
   if (tile_x) *tile_x = b->xc;
   if (items) *items = b->n_items;
   if (workgroups) {
-    const int n_perf = b->n_items - b->n_plain;
-    *workgroups = b->n_wg > 0 ? std::min(b->n_wg, b->n_plain) + std::min(b->n_wg, n_perf)
-                              : b->n_items;
+    int w = 0;
+    for (const auto& G : b->groups)
+      w += b->n_wg > 0 ? std::min(b->n_wg, G.plain1 - G.plain0) +
+                             std::min(b->n_wg, G.perf1 - G.perf0)
+                       : (G.plain1 - G.plain0) + (G.perf1 - G.perf0);
+    *workgroups = w;
   }
+  if (groups) *groups = (int)b->groups.size();
   return RFA_OK;
 }
 

@@ -78,10 +78,12 @@ hipError_t launch_step_naive(Grid3 g, const StepBuffers& b, const StepConst& K,
 hipError_t launch_reduce_partials(const float* partials, int n_slots, int nwg,
                                   double* acc, hipStream_t st);
 
-// Per-instance sums of batch partials [n_slots][n_items][3]: instance i
-// owns items [first[2 i], first[2 i + 1]); acc[3 i + c] += its sum.
+// Per-instance sums of batch partials [n_slots][n_items][3] for instances
+// inst0 .. inst0 + n_inst - 1: instance i owns items [first[2 i],
+// first[2 i + 1]); acc[3 i + c] += its sum.
 hipError_t launch_reduce_batch(const float* partials, int n_slots, int n_items,
-                               const int* first, int n_inst, double* acc, hipStream_t st);
+                               const int* first, int inst0, int n_inst, double* acc,
+                               hipStream_t st);
 
 // ---- setup ---------------------------------------------------------------
 // Build internal label bytes from class labels; counts labels >= n_classes.

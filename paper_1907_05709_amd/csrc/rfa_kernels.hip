@@ -188,10 +188,10 @@ hipError_t launch_reduce_partials(const float* partials, int n_slots, int nwg, d
 // Batched diagnostics: block i sums, in fixed order, the partials of
 // instance i's items over n_slots steps into acc[3 i .. 3 i + 2].
 __global__ __launch_bounds__(256) void k_reduce_batch(const float* partials, int n_slots,
-                                                      int n_items, const int* first,
+                                                      int n_items, const int* first, int inst0,
                                                       double* acc) {
   __shared__ double sh[3][4];
-  const int i = blockIdx.x;
+  const int i = inst0 + blockIdx.x;
   const int a = first[2 * i], cnt = first[2 * i + 1] - first[2 * i];
   double v0 = 0.0, v1 = 0.0, v2 = 0.0;
   for (int e = threadIdx.x; e < n_slots * cnt; e += 256) {
@@ -217,9 +217,10 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const float* partials, int
 }
 
 hipError_t launch_reduce_batch(const float* partials, int n_slots, int n_items,
-                               const int* first, int n_inst, double* acc, hipStream_t st) {
+                               const int* first, int inst0, int n_inst, double* acc,
+                               hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_batch, dim3(n_inst), dim3(256), 0, st, partials, n_slots,
-                     n_items, first, acc);
+                     n_items, first, inst0, acc);
   return hipGetLastError();
 }
 

@@ -91,8 +91,8 @@ _SIGS = {
     "rfa_batch_create": [C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_double),
                          C.POINTER(C.c_void_p)],
     "rfa_batch_step": [C.c_void_p, C.c_int, C.c_void_p],
-    "rfa_batch_set_plan": [C.c_void_p, C.c_int, C.c_int, C.c_int],
-    "rfa_batch_get_plan": [C.c_void_p] + [C.POINTER(C.c_int)] * 4,
+    "rfa_batch_set_plan": [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_longlong],
+    "rfa_batch_get_plan": [C.c_void_p] + [C.POINTER(C.c_int)] * 5,
     "rfa_batch_last_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
     "rfa_batch_destroy": [C.c_void_p],
     "rfa_destroy_grid": [C.c_void_p],
@@ -321,14 +321,17 @@ def rfa_batch_step(b, n_steps: int, n_grids: int = 0, want_diag: bool = False):
     return [d.as_dict() for d in diags] if want_diag else None
 
 
-def rfa_batch_set_plan(b, tile_y: int = 0, tile_x: int = 0, workgroups: int = 0):
-    _check(lib().rfa_batch_set_plan(b, int(tile_y), int(tile_x), int(workgroups)))
+def rfa_batch_set_plan(b, tile_y: int = 0, tile_x: int = 0, workgroups: int = 0,
+                       group_voxels: int = -1):
+    _check(lib().rfa_batch_set_plan(b, int(tile_y), int(tile_x), int(workgroups),
+                                    int(group_voxels)))
 
 
 def rfa_batch_get_plan(b) -> dict:
-    v = [C.c_int() for _ in range(4)]
+    v = [C.c_int() for _ in range(5)]
     _check(lib().rfa_batch_get_plan(b, *[C.byref(x) for x in v]))
-    return dict(zip(("tile_y", "tile_x", "items", "workgroups"), [x.value for x in v]))
+    return dict(zip(("tile_y", "tile_x", "items", "workgroups", "groups"),
+                    [x.value for x in v]))
 
 
 def rfa_batch_last_time(b):
@@ -552,8 +555,9 @@ class Batch:
         """(device ms of the last step call, voxel-steps it advanced)."""
         return rfa_batch_last_time(self.h)
 
-    def set_plan(self, tile_y: int = 0, tile_x: int = 0, workgroups: int = 0):
-        rfa_batch_set_plan(self.h, tile_y, tile_x, workgroups)
+    def set_plan(self, tile_y: int = 0, tile_x: int = 0, workgroups: int = 0,
+                 group_voxels: int = -1):
+        rfa_batch_set_plan(self.h, tile_y, tile_x, workgroups, group_voxels)
         return self.plan()
 
     def plan(self) -> dict:

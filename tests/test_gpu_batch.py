@@ -37,13 +37,21 @@ def state(g):
     return hi, lo, m, om
 
 
-def test_batch_bitwise_equals_single_grids_and_replays():
+@pytest.mark.parametrize("group_voxels", [-1, 120_000, 0])
+def test_batch_bitwise_equals_single_grids_and_replays(group_voxels):
+    """Default grouping, several small groups (each runs all its steps before
+    the next), and all grids in lockstep."""
     from paper_1907_05709_amd import rfa
     cases = small_sweep()
     assert len({c.shape for c in cases}) > 2          # uneven grids
     singles = [grid_for(c) for c in cases]
     batched = [grid_for(c) for c in cases]
     b = rfa.Batch(batched, [c.dt for c in cases])
+    plan = b.set_plan(0, 0, 0, group_voxels)
+    if group_voxels == 120_000:
+        assert plan["groups"] > 1
+    elif group_voxels == 0:
+        assert plan["groups"] == 1
     schedule = [37, 12, 37, 1]                        # odd counts, replayed graph
     for n in schedule:
         for g, c in zip(singles, cases):
@@ -118,12 +126,14 @@ def test_batch_resyncs_after_a_grid_is_stepped_alone():
         g.close()
 
 
-def test_batch_diagnostics_match_single_grids():
+@pytest.mark.parametrize("group_voxels", [-1, 100_000])
+def test_batch_diagnostics_match_single_grids(group_voxels):
     from paper_1907_05709_amd import rfa
     cases = small_sweep(n_inst=4, seed=4300)
     singles = [grid_for(c) for c in cases]
     batched = [grid_for(c) for c in cases]
     b = rfa.Batch(batched, [c.dt for c in cases])
+    b.set_plan(0, 0, 0, group_voxels)
     d_b = b.step(70, diag=True)                       # crosses a reduction boundary
     for g, c, db in zip(singles, cases, d_b):
         ds = g.step(70, c.dt, diag=True)
