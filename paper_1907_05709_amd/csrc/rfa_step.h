@@ -15,15 +15,16 @@ constexpr int kMaxDepth = 2;
 enum StepKind { kStepNaive = 1, kStepTiled = 2 };
 
 struct StepPlan {
-  int kind;    // StepKind
-  int depth;   // steps per launch (1, or 2 with the tiled kernel)
-  int ty;      // tile rows (y) per work-group (tiled)
-  int xc;      // x planes per work-group (tiled)
-  int nwg;     // work-groups per launch (stride of the partials)
-  int zv;      // consecutive z voxels per lane (tiled, one step per launch)
+  int kind = 0;    // StepKind
+  int depth = 1;   // steps per launch (1, or 2 with the tiled kernel)
+  int ty = 4;      // tile rows (y) per work-group (tiled)
+  int xc = 1;      // x planes per work-group (tiled)
+  int nwg = 0;     // work-groups per launch (stride of the partials)
+  int zv = 1;      // consecutive z voxels per lane (tiled, one step per launch)
+  int stream = 0;  // streaming stores (working set beyond the last-level cache)
   // one-step plan for step counts not divisible by depth (equal to the
   // plan itself when depth == 1)
-  int one_kind, one_ty, one_xc, one_nwg, one_zv;
+  int one_kind = 0, one_ty = 4, one_xc = 1, one_nwg = 0, one_zv = 1;
 };
 
 StepPlan plan_naive(Grid3 g);

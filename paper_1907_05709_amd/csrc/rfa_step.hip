@@ -9,6 +9,11 @@ namespace rfa {
 
 namespace {
 constexpr int kTargetWg = 1024;  // ~4 work-groups per CU on 256 CUs
+
+// Stepping working set (two state images, class bytes, source, damage:
+// ~29 B per voxel) beyond ~3/4 of the 256 MB last-level cache: stream the
+// stores instead of writing them through.
+int stream_for(Grid3 g) { return (double)g.n() * 29.0 > 192.0 * (1 << 20) ? 1 : 0; }
 }
 
 namespace {
@@ -18,6 +23,11 @@ StepPlan with_one(StepPlan p, const StepPlan& one) {
   p.one_xc = one.xc;
   p.one_nwg = one.nwg;
   p.one_zv = one.zv;
+  return p;
+}
+
+StepPlan with_store(StepPlan p, Grid3 g) {
+  p.stream = stream_for(g);
   return p;
 }
 
@@ -42,6 +52,7 @@ StepPlan plan_naive(Grid3 g) {
   p.xc = 1;
   p.nwg = naive_wg_count(g);
   p.zv = 1;
+  p.stream = 0;
   return with_one(p, p);
 }
 
@@ -54,7 +65,7 @@ StepPlan plan_tiled(Grid3 g, int ty, int xc) {
   p.xc = xc;
   p.nwg = s.nwg;
   p.zv = 1;
-  return with_one(p, p);
+  return with_one(with_store(p, g), p);
 }
 
 StepPlan plan_wide(Grid3 g, int zv, int ty, int xc) {
@@ -66,7 +77,7 @@ StepPlan plan_wide(Grid3 g, int zv, int ty, int xc) {
   p.xc = xc;
   p.nwg = s.nwg;
   p.zv = zv;
-  return with_one(p, p);
+  return with_one(with_store(p, g), p);
 }
 
 StepPlan plan_tiled2(Grid3 g, int ty, int xc) {
@@ -78,7 +89,7 @@ StepPlan plan_tiled2(Grid3 g, int ty, int xc) {
   p.xc = xc;
   p.nwg = s.nwg;
   p.zv = 1;
-  return with_one(p, plan_default(g, kStepTiled, 1, 0, 0, 0));
+  return with_one(with_store(p, g), plan_default(g, kStepTiled, 1, 0, 0, 0));
 }
 
 StepPlan plan_one(const StepPlan& p) {
@@ -160,10 +171,13 @@ int plan_max_wg(Grid3 g) {
 hipError_t launch_plan(Grid3 g, const StepPlan& plan, const StepBuffers& b, const StepConst& K,
                        hipStream_t st) {
   if (plan.kind == kStepNaive) return launch_step_naive(g, b, K, st);
-  if (plan.depth == 2) return launch_step_tiled2(tiled2_shape(g, plan.ty, plan.xc), g, b, K, st);
+  const bool stream = plan.stream != 0;
+  if (plan.depth == 2)
+    return launch_step_tiled2(tiled2_shape(g, plan.ty, plan.xc), g, b, K, stream, st);
   if (plan.zv > 1)
-    return launch_step_wide(plan.zv, wide_shape(g, plan.zv, plan.ty, plan.xc), g, b, K, st);
-  return launch_step_tiled(tiled_shape(g, plan.ty, plan.xc), g, b, K, st);
+    return launch_step_wide(plan.zv, wide_shape(g, plan.zv, plan.ty, plan.xc), g, b, K, stream,
+                            st);
+  return launch_step_tiled(tiled_shape(g, plan.ty, plan.xc), g, b, K, stream, st);
 }
 
 rfa_status run_steps(Grid3 g, const StepPlan& plan, StepState& s, const StepConst& K,

@@ -17,6 +17,17 @@ constexpr int kRsrcWord3 = 0x00020000;  // gfx9 buffer descriptor word 3 (32-bit
 // 2^31 bytes, so this offset (plus any in-range scalar offset) is always
 // out of range.  Used to predicate stores without a branch.
 constexpr unsigned kOob = 0x80000000u;
+// Cache policies of the kernels' stores (cache-policy bits of gfx950 buffer
+// instructions), chosen by measurement per schedule.  kStoreThrough (sc1)
+// writes through to the device-coherent level, so little dirty data is left
+// in the per-XCD L2s to write back when a short launch ends: best for one
+// grid whose working set stays in the last-level cache between launches.
+// kStoreStream (nt) marks the data as streaming: best when the working set
+// exceeds that cache.  kStoreBack (no bits) is the ordinary write-back
+// policy, best for the longer launches of cache-sized batch groups.
+constexpr int kStoreThrough = 16;
+constexpr int kStoreStream = 2;
+constexpr int kStoreBack = 0;
 
 // Hardware places work-group w on XCD w % 8.  Give XCD k the contiguous range
 // of logical tiles [base_k, base_k + count_k), so tiles sharing halo rows
@@ -40,16 +51,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, si
 __device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
   return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
 }
+template <int AUX = kStoreThrough>
 __device__ __forceinline__ void st_f32(float v, __amdgpu_buffer_rsrc_t r, unsigned voff,
                                        int soff) {
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, soff, AUX);
 }
 __device__ __forceinline__ unsigned ld_u8(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
   return (unsigned)__builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, soff, 0);
 }
+template <int AUX = kStoreThrough>
 __device__ __forceinline__ void st_u8(unsigned v, __amdgpu_buffer_rsrc_t r, unsigned voff,
                                       int soff) {
-  __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, r, (int)voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, r, (int)voff, soff, AUX);
 }
 
 // Stage the coefficient tables of the nc classes in use into LDS.

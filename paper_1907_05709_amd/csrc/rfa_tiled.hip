@@ -107,7 +107,7 @@ struct TileSmem {
 // Tables must be staged (a barrier inside the march orders them).  The
 // work-group's partial sums are written to partials[wg_slot * 3] if
 // partials is not null.
-template <int TY>
+template <int TY, int AUX>
 __device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& b,
                                            const StepConst& K, bool perf, int nx, int ny,
                                            int nz, int xc, int tz, int ty, int tx,
@@ -206,10 +206,10 @@ __device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& 
     {
       const int so = (min(x, c.x1 - 1) - c.xb) * (int)c.psz;  // uniform
       const unsigned v4 = valid ? st4 : kOob;
-      st_f32(nh, c.r.hi_out, v4, so * 4);
-      st_f32(nl, c.r.lo_out, v4, so * 4);
-      st_f32(om, c.r.om, v4, so * 4);
-      st_u8(nlab, c.r.lab, (valid && nlab != P.b) ? st1 : kOob, so);
+      st_f32<AUX>(nh, c.r.hi_out, v4, so * 4);
+      st_f32<AUX>(nl, c.r.lo_out, v4, so * 4);
+      st_f32<AUX>(om, c.r.om, v4, so * 4);
+      st_u8<AUX>(nlab, c.r.lab, (valid && nlab != P.b) ? st1 : kOob, so);
     }
     hm = P.h;
     lm = P.l;
@@ -233,7 +233,7 @@ __device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& 
 
 }  // namespace
 
-template <int TY, bool PERF>
+template <int TY, bool PERF, int AUX>
 __global__ __launch_bounds__(64 * TY) void k_step_tiled(StepBuffers b, StepConst K, int nx,
                                                         int ny, int nz, int xc, int tiles_z,
                                                         int tiles_y, int nwg) {
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled(StepBuffers b, StepConst
   const int tz = wg % tiles_z;
   const int ty = (wg / tiles_z) % tiles_y;
   const int tx = wg / (tiles_z * tiles_y);
-  tile_march<TY>(sm, b, K, PERF, nx, ny, nz, xc, tz, ty, tx, b.partials, wg);
+  tile_march<TY, AUX>(sm, b, K, PERF, nx, ny, nz, xc, tz, ty, tx, b.partials, wg);
 }
 
 // Batched step over the work list of all instances (items grouped by
@@ -292,7 +292,9 @@ __global__ __launch_bounds__(64 * TY) void k_step_batch(const BatchInstance* ins
     K.cap = uf(I.K.cap);
     K.thr = uf(I.K.thr);
     stage_tables(sm.cf, sm.cls, b.tab, b.n_classes, 64 * TY);
-    tile_march<TY>(sm, b, K, PERF, ui(I.nx), ui(I.ny), ui(I.nz), ui(I.xc), ui(w.tz), ui(w.ty),
+    // groups of a batch are sized to stay in the last-level cache
+    tile_march<TY, kStoreBack>(sm, b, K, PERF, ui(I.nx), ui(I.ny), ui(I.nz), ui(I.xc),
+                               ui(w.tz), ui(w.ty),
                    ui(w.tx), partials, it);
   };
   if (LOOP) {
@@ -334,17 +336,24 @@ bool tiled_fits(Grid3 g, int xc) {
   return (double)(xc + kAhead + 2) * g.ny * g.nz * 4.0 < 2147483647.0;
 }
 
-template <int TY>
+template <int TY, int AUX>
 static hipError_t launch_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
                             const StepConst& K, hipStream_t st) {
   dim3 grid(s.nwg), block(64 * TY);
   if (b.perf)
-    hipLaunchKernelGGL((k_step_tiled<TY, true>), grid, block, 0, st, b, K, g.nx, g.ny, g.nz,
-                       s.xc, s.tiles_z, s.tiles_y, s.nwg);
+    hipLaunchKernelGGL((k_step_tiled<TY, true, AUX>), grid, block, 0, st, b, K, g.nx, g.ny,
+                       g.nz, s.xc, s.tiles_z, s.tiles_y, s.nwg);
   else
-    hipLaunchKernelGGL((k_step_tiled<TY, false>), grid, block, 0, st, b, K, g.nx, g.ny, g.nz,
-                       s.xc, s.tiles_z, s.tiles_y, s.nwg);
+    hipLaunchKernelGGL((k_step_tiled<TY, false, AUX>), grid, block, 0, st, b, K, g.nx, g.ny,
+                       g.nz, s.xc, s.tiles_z, s.tiles_y, s.nwg);
   return hipGetLastError();
+}
+
+template <int TY>
+static hipError_t launch_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
+                            const StepConst& K, bool stream, hipStream_t st) {
+  return stream ? launch_ty<TY, kStoreStream>(s, g, b, K, st)
+                : launch_ty<TY, kStoreThrough>(s, g, b, K, st);
 }
 
 hipError_t launch_step_batch(int ty, bool perf, const BatchInstance* inst,
@@ -365,12 +374,12 @@ hipError_t launch_step_batch(int ty, bool perf, const BatchInstance* inst,
 }
 
 hipError_t launch_step_tiled(const TiledShape& s, Grid3 g, const StepBuffers& b,
-                             const StepConst& K, hipStream_t st) {
+                             const StepConst& K, bool stream, hipStream_t st) {
   if (!tiled_fits(g, s.xc)) return hipErrorInvalidValue;
   switch (s.ty) {
-    case 4: return launch_ty<4>(s, g, b, K, st);
-    case 8: return launch_ty<8>(s, g, b, K, st);
-    case 16: return launch_ty<16>(s, g, b, K, st);
+    case 4: return launch_ty<4>(s, g, b, K, stream, st);
+    case 8: return launch_ty<8>(s, g, b, K, stream, st);
+    case 16: return launch_ty<16>(s, g, b, K, stream, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -69,7 +69,7 @@ struct Tile2Smem {
 
 }  // namespace
 
-template <int TY, bool PERF>
+template <int TY, bool PERF, int AUX>
 __global__ __launch_bounds__(64 * TY) void k_step_tiled2(StepBuffers b, StepConst K, int nx,
                                                          int ny, int nz, int xc, int tiles_z,
                                                          int tiles_y, int nwg) {
@@ -220,10 +220,10 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled2(StepBuffers b, StepCons
                  p2);
       const int so = (min(max(j - 1, x0), x1 - 1) - xb) * (int)psz;  // uniform
       const unsigned v4 = keep ? col * 4 : kOob;
-      st_f32(h2, r_hio, v4, so * 4);
-      st_f32(l2, r_loo, v4, so * 4);
-      st_f32(om2, r_om, v4, so * 4);
-      st_u8(b2, r_lab, (keep && b2 != Q.b) ? col : kOob, so);
+      st_f32<AUX>(h2, r_hio, v4, so * 4);
+      st_f32<AUX>(l2, r_loo, v4, so * 4);
+      st_f32<AUX>(om2, r_om, v4, so * 4);
+      st_u8<AUX>(b2, r_lab, (keep && b2 != Q.b) ? col : kOob, so);
       acc.perf += keep ? p2.perf : 0.0f;
       acc.bnd += keep ? p2.bnd : 0.0f;
       acc.mono += keep ? p2.mono : 0u;
@@ -275,25 +275,32 @@ bool tiled2_fits(Grid3 g, int xc) {
   return (double)(xc + 4) * g.ny * g.nz * 4.0 < 2147483647.0;
 }
 
-template <int TY>
+template <int TY, int AUX>
 static hipError_t launch2_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
                              const StepConst& K, hipStream_t st) {
   dim3 grid(s.nwg), block(64 * TY);
   if (b.perf)
-    hipLaunchKernelGGL((k_step_tiled2<TY, true>), grid, block, 0, st, b, K, g.nx, g.ny, g.nz,
-                       s.xc, s.tiles_z, s.tiles_y, s.nwg);
+    hipLaunchKernelGGL((k_step_tiled2<TY, true, AUX>), grid, block, 0, st, b, K, g.nx, g.ny,
+                       g.nz, s.xc, s.tiles_z, s.tiles_y, s.nwg);
   else
-    hipLaunchKernelGGL((k_step_tiled2<TY, false>), grid, block, 0, st, b, K, g.nx, g.ny, g.nz,
-                       s.xc, s.tiles_z, s.tiles_y, s.nwg);
+    hipLaunchKernelGGL((k_step_tiled2<TY, false, AUX>), grid, block, 0, st, b, K, g.nx, g.ny,
+                       g.nz, s.xc, s.tiles_z, s.tiles_y, s.nwg);
   return hipGetLastError();
 }
 
+template <int TY>
+static hipError_t launch2_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
+                             const StepConst& K, bool stream, hipStream_t st) {
+  return stream ? launch2_ty<TY, kStoreStream>(s, g, b, K, st)
+                : launch2_ty<TY, kStoreThrough>(s, g, b, K, st);
+}
+
 hipError_t launch_step_tiled2(const TiledShape& s, Grid3 g, const StepBuffers& b,
-                              const StepConst& K, hipStream_t st) {
+                              const StepConst& K, bool stream, hipStream_t st) {
   if (!tiled2_fits(g, s.xc)) return hipErrorInvalidValue;
   switch (s.ty) {
-    case 8: return launch2_ty<8>(s, g, b, K, st);
-    case 16: return launch2_ty<16>(s, g, b, K, st);
+    case 8: return launch2_ty<8>(s, g, b, K, stream, st);
+    case 16: return launch2_ty<16>(s, g, b, K, stream, st);
     default: return hipErrorInvalidValue;
   }
 }

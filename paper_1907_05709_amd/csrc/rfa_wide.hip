@@ -58,15 +58,15 @@ __device__ __forceinline__ typename Vec<ZV>::f ldv(__amdgpu_buffer_rsrc_t r, uns
     return __builtin_bit_cast(typename Vec<2>::f,
                               __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0));
 }
-template <int ZV>
+template <int ZV, int AUX>
 __device__ __forceinline__ void stv(typename Vec<ZV>::f v, __amdgpu_buffer_rsrc_t r,
                                    unsigned voff, int soff) {
   if constexpr (ZV == 4)
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(typename Vec<4>::u, v), r,
-                                           (int)voff, soff, 0);
+                                           (int)voff, soff, AUX);
   else
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(typename Vec<2>::u, v), r,
-                                          (int)voff, soff, 0);
+                                          (int)voff, soff, AUX);
 }
 // ZV class bytes as one word
 template <int ZV>
@@ -76,13 +76,13 @@ __device__ __forceinline__ unsigned ldb(__amdgpu_buffer_rsrc_t r, unsigned voff,
   else
     return (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, soff, 0);
 }
-template <int ZV>
+template <int ZV, int AUX>
 __device__ __forceinline__ void stb(unsigned v, __amdgpu_buffer_rsrc_t r, unsigned voff,
                                    int soff) {
   if constexpr (ZV == 4)
-    __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, soff, AUX);
   else
-    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, (int)voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, (int)voff, soff, AUX);
 }
 __device__ __forceinline__ unsigned byte_of(unsigned w, int k) { return (w >> (8 * k)) & 0xFFu; }
 
@@ -115,7 +115,7 @@ struct WideSmem {
 
 }  // namespace
 
-template <int ZV, int TY, bool PERF>
+template <int ZV, int TY, bool PERF, int AUX>
 __global__ __launch_bounds__(64 * TY) void k_step_wide(StepBuffers b, StepConst K, int nx,
                                                        int ny, int nz, int xc, int tiles_z,
                                                        int tiles_y, int nwg) {
@@ -265,11 +265,11 @@ __global__ __launch_bounds__(64 * TY) void k_step_wide(StepBuffers b, StepConst 
     {
       const int so = (min(x, x1 - 1) - xb) * (int)psz;  // uniform
       const unsigned v4 = valid ? st4 : kOob;
-      stv<ZV>(nh, r_hio, v4, so * 4);
-      stv<ZV>(nl, r_loo, v4, so * 4);
-      stv<ZV>(om, r_om, v4, so * 4);
+      stv<ZV, AUX>(nh, r_hio, v4, so * 4);
+      stv<ZV, AUX>(nl, r_loo, v4, so * 4);
+      stv<ZV, AUX>(om, r_om, v4, so * 4);
       // past the chunk the computed bytes carry the held flag: never stored
-      stb<ZV>(nlab, r_lab, (valid && nlab != P.b) ? st1 : kOob, so);
+      stb<ZV, AUX>(nlab, r_lab, (valid && nlab != P.b) ? st1 : kOob, so);
     }
     hm = P.h;
     lm = P.l;
@@ -308,26 +308,33 @@ bool wide_fits(Grid3 g, int zv, int xc) {
          (double)(xc + 2) * g.ny * g.nz * 4.0 < 2147483647.0;
 }
 
-template <int ZV, int TY>
+template <int ZV, int TY, int AUX>
 static hipError_t launch_wide_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
                                  const StepConst& K, hipStream_t st) {
   dim3 grid(s.nwg), block(64 * TY);
   if (b.perf)
-    hipLaunchKernelGGL((k_step_wide<ZV, TY, true>), grid, block, 0, st, b, K, g.nx, g.ny, g.nz,
-                       s.xc, s.tiles_z, s.tiles_y, s.nwg);
+    hipLaunchKernelGGL((k_step_wide<ZV, TY, true, AUX>), grid, block, 0, st, b, K, g.nx, g.ny,
+                       g.nz, s.xc, s.tiles_z, s.tiles_y, s.nwg);
   else
-    hipLaunchKernelGGL((k_step_wide<ZV, TY, false>), grid, block, 0, st, b, K, g.nx, g.ny,
+    hipLaunchKernelGGL((k_step_wide<ZV, TY, false, AUX>), grid, block, 0, st, b, K, g.nx, g.ny,
                        g.nz, s.xc, s.tiles_z, s.tiles_y, s.nwg);
   return hipGetLastError();
 }
 
+template <int ZV, int TY>
+static hipError_t launch_wide_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
+                                 const StepConst& K, bool stream, hipStream_t st) {
+  return stream ? launch_wide_ty<ZV, TY, kStoreStream>(s, g, b, K, st)
+                : launch_wide_ty<ZV, TY, kStoreThrough>(s, g, b, K, st);
+}
+
 hipError_t launch_step_wide(int zv, const TiledShape& s, Grid3 g, const StepBuffers& b,
-                            const StepConst& K, hipStream_t st) {
+                            const StepConst& K, bool stream, hipStream_t st) {
   if (!wide_fits(g, zv, s.xc)) return hipErrorInvalidValue;
-  if (zv == 4 && s.ty == 4) return launch_wide_ty<4, 4>(s, g, b, K, st);
-  if (zv == 4 && s.ty == 8) return launch_wide_ty<4, 8>(s, g, b, K, st);
-  if (zv == 2 && s.ty == 4) return launch_wide_ty<2, 4>(s, g, b, K, st);
-  if (zv == 2 && s.ty == 8) return launch_wide_ty<2, 8>(s, g, b, K, st);
+  if (zv == 4 && s.ty == 4) return launch_wide_ty<4, 4>(s, g, b, K, stream, st);
+  if (zv == 4 && s.ty == 8) return launch_wide_ty<4, 8>(s, g, b, K, stream, st);
+  if (zv == 2 && s.ty == 4) return launch_wide_ty<2, 4>(s, g, b, K, stream, st);
+  if (zv == 2 && s.ty == 8) return launch_wide_ty<2, 8>(s, g, b, K, stream, st);
   return hipErrorInvalidValue;
 }
 
