@@ -241,6 +241,14 @@ StepConst step_const(rfa_grid g, double dt) {
   return K;
 }
 
+// Re-derive an automatic launch plan after the perfusion field came or went
+// (a plan from rfa_tune or explicit options stays).
+void refresh_plan(rfa_grid g) {
+  if (g->plan_tuned) return;
+  g->plan = plan_default(g->g, g->opt.kernel, g->opt.depth, g->opt.tile_y, g->opt.tile_x,
+                         g->opt.z_vec, g->perf != nullptr);
+}
+
 rfa_status compute_dt_max(rfa_grid g) {
   int nblk = 0;
   HIP_TRY(launch_dt_bound(g->g, g->lab, g->perf, g->cp_dev, 1.0 / (g->dx * g->dx),
@@ -724,6 +732,7 @@ rfa_status rfa_set_perfusion(rfa_grid g, const float* factor) {
   if (!factor) {
     if (g->perf) (void)hipFree(g->perf);
     g->perf = nullptr;
+    refresh_plan(g);
     return compute_dt_max(g);
   }
   if (!g->opt.inputs_on_device) {
@@ -736,6 +745,7 @@ rfa_status rfa_set_perfusion(rfa_grid g, const float* factor) {
     if (s != RFA_OK) return s;
   }
   HIP_TRY(hipMemcpyAsync(g->perf, factor, n * sizeof(float), kind_in(g), g->st));
+  refresh_plan(g);
   return compute_dt_max(g);
 }
 
@@ -1153,6 +1163,7 @@ rfa_status rfa_set_perfusion_bspline(rfa_grid g, int m, const float* ctrl) {
   HIP_TRY(hipStreamSynchronize(g->st));
   g->bs_m = m;
   ++g->version;
+  refresh_plan(g);
   return compute_dt_max(g);
 }
 
