@@ -121,6 +121,11 @@ typedef struct {
   int z_vec;          /* tiled one-step kernel: consecutive z voxels per
                          lane, 1, 2 or 4 (2 and 4 need nz divisible by it,
                          tile_y 4 or 8; otherwise 1 is used); 0 = auto (0)   */
+  int store_policy;   /* tiled kernels' store cache policy: 1 write-back,
+                         2 write-through (sc1), 3 streaming (nt); 0 = auto:
+                         streaming when the stepping working set exceeds
+                         ~3/4 of the 256 MB last-level cache, else
+                         write-through (0)                                   */
 } rfa_options;
 
 /* Diagnostics of one rfa_step call (energies relative to 37 degC, J). */

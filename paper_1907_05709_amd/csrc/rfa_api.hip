@@ -246,7 +246,7 @@ StepConst step_const(rfa_grid g, double dt) {
 void refresh_plan(rfa_grid g) {
   if (g->plan_tuned) return;
   g->plan = plan_default(g->g, g->opt.kernel, g->opt.depth, g->opt.tile_y, g->opt.tile_x,
-                         g->opt.z_vec, g->perf != nullptr);
+                         g->opt.z_vec, g->perf != nullptr, g->opt.store_policy);
 }
 
 rfa_status compute_dt_max(rfa_grid g) {
@@ -525,6 +525,7 @@ rfa_status rfa_default_options(rfa_options* opt) {
   opt->tile_x = 0;
   opt->time_kernels = 0;
   opt->z_vec = 0;
+  opt->store_policy = 0;
   return RFA_OK;
 }
 
@@ -554,6 +555,8 @@ rfa_status rfa_create_grid(int nx, int ny, int nz, double dx, double dy, double 
   if (o.tile_x < 0) return fail(RFA_ERR_ARG, "tile_x must be >= 0");
   if (o.z_vec != 0 && o.z_vec != 1 && o.z_vec != 2 && o.z_vec != 4)
     return fail(RFA_ERR_ARG, "z_vec must be 0, 1, 2 or 4");
+  if (o.store_policy < 0 || o.store_policy > 3)
+    return fail(RFA_ERR_ARG, "store_policy must be 0, 1, 2 or 3");
   if (o.time_kernels < 0 || o.time_kernels > kTimedBatch)
     return fail(RFA_ERR_ARG, "time_kernels must be in 0..%d", kTimedBatch);
   rfa_grid g = new (std::nothrow) rfa_grid_s();
@@ -569,7 +572,8 @@ rfa_status rfa_create_grid(int nx, int ny, int nz, double dx, double dy, double 
     return fail(RFA_ERR_HIP, "no HIP device");
   }
   const size_t n = g->g.n();
-  g->plan = plan_default(g->g, o.kernel, o.depth, o.tile_y, o.tile_x, o.z_vec);
+  g->plan = plan_default(g->g, o.kernel, o.depth, o.tile_y, o.tile_x, o.z_vec, false,
+                         o.store_policy);
   const size_t nwg = (size_t)plan_max_wg(g->g);
   g->partial_floats = nwg * 3 * kPartialSlots;
   g->red_doubles = 4 * 1024 + 64;
@@ -1056,6 +1060,8 @@ rfa_status rfa_tune(rfa_grid g, double dt, int reps) {
   double best_ms = 1e300;
   StepPlan best = g->plan;
   hipError_t e = hipSuccess;
+  if (g->opt.store_policy > 0)  // a requested store policy holds for every candidate
+    for (int c = 0; c < nc; ++c) cand[c].store = g->opt.store_policy - 1;
   for (int c = 0; c < nc && e == hipSuccess; ++c) {
     if ((e = hipMemcpyAsync(om2, g->om, n * sizeof(float), hipMemcpyDeviceToDevice, g->st))) break;
     if ((e = hipMemcpyAsync(lab2, g->lab, n, hipMemcpyDeviceToDevice, g->st))) break;

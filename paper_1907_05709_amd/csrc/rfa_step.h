@@ -21,7 +21,7 @@ struct StepPlan {
   int xc = 1;      // x planes per work-group (tiled)
   int nwg = 0;     // work-groups per launch (stride of the partials)
   int zv = 1;      // consecutive z voxels per lane (tiled, one step per launch)
-  int stream = 0;  // streaming stores (working set beyond the last-level cache)
+  int store = 0;   // StorePolicy of the step launches
   // one-step plan for step counts not divisible by depth (equal to the
   // plan itself when depth == 1)
   int one_kind = 0, one_ty = 4, one_xc = 1, one_nwg = 0, one_zv = 1;
@@ -33,10 +33,11 @@ StepPlan plan_tiled2(Grid3 g, int ty, int xc);
 StepPlan plan_wide(Grid3 g, int zv, int ty, int xc);
 // The one-step plan that accompanies a plan.
 StepPlan plan_one(const StepPlan& p);
-// Heuristic plan from the options (kernel, depth, tile_y, tile_x, z_vec;
-// 0 = automatic); perf: the grid carries a perfusion field.
+// Heuristic plan from the options (kernel, depth, tile_y, tile_x, z_vec,
+// store = 1 + StorePolicy; 0 = automatic); perf: the grid carries a
+// perfusion field.
 StepPlan plan_default(Grid3 g, int kernel, int depth, int tile_y, int tile_x, int zv,
-                      bool perf = false);
+                      bool perf = false, int store = 0);
 // Candidate plans for tuning (depth 1, and depth 2 if max_depth >= 2).
 int plan_candidates(Grid3 g, int max_depth, StepPlan* out, int max_out);
 // Largest partial stride any plan of this grid can need.

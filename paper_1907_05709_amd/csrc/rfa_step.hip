@@ -13,7 +13,9 @@ constexpr int kTargetWg = 1024;  // ~4 work-groups per CU on 256 CUs
 // Stepping working set (two state images, class bytes, source, damage:
 // ~29 B per voxel) beyond ~3/4 of the 256 MB last-level cache: stream the
 // stores instead of writing them through.
-int stream_for(Grid3 g) { return (double)g.n() * 29.0 > 192.0 * (1 << 20) ? 1 : 0; }
+int store_for(Grid3 g) {
+  return (double)g.n() * 29.0 > 192.0 * (1 << 20) ? kPolicyStream : kPolicyThrough;
+}
 }
 
 namespace {
@@ -27,7 +29,7 @@ StepPlan with_one(StepPlan p, const StepPlan& one) {
 }
 
 StepPlan with_store(StepPlan p, Grid3 g) {
-  p.stream = stream_for(g);
+  p.store = store_for(g);
   return p;
 }
 
@@ -52,7 +54,7 @@ StepPlan plan_naive(Grid3 g) {
   p.xc = 1;
   p.nwg = naive_wg_count(g);
   p.zv = 1;
-  p.stream = 0;
+  p.store = kPolicyBack;
   return with_one(p, p);
 }
 
@@ -103,8 +105,9 @@ StepPlan plan_one(const StepPlan& p) {
   return o;
 }
 
-StepPlan plan_default(Grid3 g, int kernel, int depth, int tile_y, int tile_x, int zv,
-                      bool perf) {
+namespace {
+StepPlan default_shape(Grid3 g, int kernel, int depth, int tile_y, int tile_x, int zv,
+                       bool perf) {
   if (kernel == kStepNaive || !tiled_fits(g, 4)) return plan_naive(g);
   // automatic: four z voxels per lane once a tile row spans 256 voxels, two
   // (with 8-row tiles) from 96 without a perfusion field (with one, the
@@ -131,6 +134,14 @@ StepPlan plan_default(Grid3 g, int kernel, int depth, int tile_y, int tile_x, in
   int xc = tile_x ? std::min(tile_x, g.nx) : default_xc(g, tiles);
   while (xc > 4 && !tiled_fits(g, xc)) xc /= 2;
   return plan_tiled(g, ty, xc);
+}
+}  // namespace
+
+StepPlan plan_default(Grid3 g, int kernel, int depth, int tile_y, int tile_x, int zv,
+                      bool perf, int store) {
+  StepPlan p = default_shape(g, kernel, depth, tile_y, tile_x, zv, perf);
+  if (store > 0 && p.kind != kStepNaive) p.store = store - 1;
+  return p;
 }
 
 int plan_candidates(Grid3 g, int max_depth, StepPlan* out, int max_out) {
@@ -175,13 +186,12 @@ int plan_max_wg(Grid3 g) {
 hipError_t launch_plan(Grid3 g, const StepPlan& plan, const StepBuffers& b, const StepConst& K,
                        hipStream_t st) {
   if (plan.kind == kStepNaive) return launch_step_naive(g, b, K, st);
-  const bool stream = plan.stream != 0;
   if (plan.depth == 2)
-    return launch_step_tiled2(tiled2_shape(g, plan.ty, plan.xc), g, b, K, stream, st);
+    return launch_step_tiled2(tiled2_shape(g, plan.ty, plan.xc), g, b, K, plan.store, st);
   if (plan.zv > 1)
-    return launch_step_wide(plan.zv, wide_shape(g, plan.zv, plan.ty, plan.xc), g, b, K, stream,
-                            st);
-  return launch_step_tiled(tiled_shape(g, plan.ty, plan.xc), g, b, K, stream, st);
+    return launch_step_wide(plan.zv, wide_shape(g, plan.zv, plan.ty, plan.xc), g, b, K,
+                            plan.store, st);
+  return launch_step_tiled(tiled_shape(g, plan.ty, plan.xc), g, b, K, plan.store, st);
 }
 
 rfa_status run_steps(Grid3 g, const StepPlan& plan, StepState& s, const StepConst& K,

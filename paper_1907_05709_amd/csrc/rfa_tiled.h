@@ -7,6 +7,9 @@
 
 namespace rfa {
 
+// Store cache policy of a step launch.
+enum StorePolicy { kPolicyBack = 0, kPolicyThrough = 1, kPolicyStream = 2 };
+
 struct TiledShape {
   int ty;        // waves (y rows of the footprint) per work-group: 4, 8 or 16
   int xc;        // x planes per work-group
@@ -48,17 +51,16 @@ hipError_t launch_step_batch(int ty, bool perf, const BatchInstance* inst,
 TiledShape tiled_shape(Grid3 g, int ty, int xc);
 // Whether a chunk of xc planes fits the kernel's 32-bit plane offsets.
 bool tiled_fits(Grid3 g, int xc);
-// stream: streaming (non-temporal) stores for working sets larger than the
-// last-level cache, else stores written through to the device-coherent level.
+// store: StorePolicy of the launch's stores.
 hipError_t launch_step_tiled(const TiledShape& s, Grid3 g, const StepBuffers& b,
-                             const StepConst& K, bool stream, hipStream_t st);
+                             const StepConst& K, int store, hipStream_t st);
 
 // One step with zv (2 or 4) consecutive z voxels per lane, ty = 4 or 8;
 // needs nz % zv == 0.
 TiledShape wide_shape(Grid3 g, int zv, int ty, int xc);
 bool wide_fits(Grid3 g, int zv, int xc);
 hipError_t launch_step_wide(int zv, const TiledShape& s, Grid3 g, const StepBuffers& b,
-                            const StepConst& K, bool stream, hipStream_t st);
+                            const StepConst& K, int store, hipStream_t st);
 
 // Two steps per launch (temporal blocking, ty = 8 or 16): tiles own
 // 62 x (ty - 2) columns and recompute a one-voxel rim of the first step.
@@ -66,6 +68,6 @@ hipError_t launch_step_wide(int zv, const TiledShape& s, Grid3 g, const StepBuff
 TiledShape tiled2_shape(Grid3 g, int ty, int xc);
 bool tiled2_fits(Grid3 g, int xc);
 hipError_t launch_step_tiled2(const TiledShape& s, Grid3 g, const StepBuffers& b,
-                              const StepConst& K, bool stream, hipStream_t st);
+                              const StepConst& K, int store, hipStream_t st);
 
 }  // namespace rfa

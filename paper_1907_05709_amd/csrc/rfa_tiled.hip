@@ -351,9 +351,12 @@ static hipError_t launch_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
 
 template <int TY>
 static hipError_t launch_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
-                            const StepConst& K, bool stream, hipStream_t st) {
-  return stream ? launch_ty<TY, kStoreStream>(s, g, b, K, st)
-                : launch_ty<TY, kStoreThrough>(s, g, b, K, st);
+                            const StepConst& K, int store, hipStream_t st) {
+  switch (store) {
+    case kPolicyThrough: return launch_ty<TY, kStoreThrough>(s, g, b, K, st);
+    case kPolicyStream: return launch_ty<TY, kStoreStream>(s, g, b, K, st);
+    default: return launch_ty<TY, kStoreBack>(s, g, b, K, st);
+  }
 }
 
 hipError_t launch_step_batch(int ty, bool perf, const BatchInstance* inst,
@@ -374,12 +377,12 @@ hipError_t launch_step_batch(int ty, bool perf, const BatchInstance* inst,
 }
 
 hipError_t launch_step_tiled(const TiledShape& s, Grid3 g, const StepBuffers& b,
-                             const StepConst& K, bool stream, hipStream_t st) {
+                             const StepConst& K, int store, hipStream_t st) {
   if (!tiled_fits(g, s.xc)) return hipErrorInvalidValue;
   switch (s.ty) {
-    case 4: return launch_ty<4>(s, g, b, K, stream, st);
-    case 8: return launch_ty<8>(s, g, b, K, stream, st);
-    case 16: return launch_ty<16>(s, g, b, K, stream, st);
+    case 4: return launch_ty<4>(s, g, b, K, store, st);
+    case 8: return launch_ty<8>(s, g, b, K, store, st);
+    case 16: return launch_ty<16>(s, g, b, K, store, st);
     default: return hipErrorInvalidValue;
   }
 }

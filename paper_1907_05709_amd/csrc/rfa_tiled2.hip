@@ -290,17 +290,20 @@ static hipError_t launch2_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
 
 template <int TY>
 static hipError_t launch2_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
-                             const StepConst& K, bool stream, hipStream_t st) {
-  return stream ? launch2_ty<TY, kStoreStream>(s, g, b, K, st)
-                : launch2_ty<TY, kStoreThrough>(s, g, b, K, st);
+                             const StepConst& K, int store, hipStream_t st) {
+  switch (store) {
+    case kPolicyThrough: return launch2_ty<TY, kStoreThrough>(s, g, b, K, st);
+    case kPolicyStream: return launch2_ty<TY, kStoreStream>(s, g, b, K, st);
+    default: return launch2_ty<TY, kStoreBack>(s, g, b, K, st);
+  }
 }
 
 hipError_t launch_step_tiled2(const TiledShape& s, Grid3 g, const StepBuffers& b,
-                              const StepConst& K, bool stream, hipStream_t st) {
+                              const StepConst& K, int store, hipStream_t st) {
   if (!tiled2_fits(g, s.xc)) return hipErrorInvalidValue;
   switch (s.ty) {
-    case 8: return launch2_ty<8>(s, g, b, K, stream, st);
-    case 16: return launch2_ty<16>(s, g, b, K, stream, st);
+    case 8: return launch2_ty<8>(s, g, b, K, store, st);
+    case 16: return launch2_ty<16>(s, g, b, K, store, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -58,15 +58,21 @@ __device__ __forceinline__ typename Vec<ZV>::f ldv(__amdgpu_buffer_rsrc_t r, uns
     return __builtin_bit_cast(typename Vec<2>::f,
                               __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0));
 }
+// A buffer store of more than 64 bits reads its data registers some cycles
+// after issue, and a VALU write to them in that window corrupts the stored
+// value.  The compiler pads that window with wait states only when the
+// store's scalar offset is an immediate (it assumes a register scalar offset
+// covers it, which does not hold under load on gfx950), so the 128-bit
+// store takes its whole offset in the vector register and a zero immediate.
 template <int ZV, int AUX>
 __device__ __forceinline__ void stv(typename Vec<ZV>::f v, __amdgpu_buffer_rsrc_t r,
-                                   unsigned voff, int soff) {
+                                   unsigned voff) {
   if constexpr (ZV == 4)
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(typename Vec<4>::u, v), r,
-                                           (int)voff, soff, AUX);
+                                           (int)voff, 0, AUX);
   else
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(typename Vec<2>::u, v), r,
-                                          (int)voff, soff, AUX);
+                                          (int)voff, 0, AUX);
 }
 // ZV class bytes as one word
 template <int ZV>
@@ -264,10 +270,11 @@ __global__ __launch_bounds__(64 * TY) void k_step_wide(StepBuffers b, StepConst 
     }
     {
       const int so = (min(x, x1 - 1) - xb) * (int)psz;  // uniform
-      const unsigned v4 = valid ? st4 : kOob;
-      stv<ZV, AUX>(nh, r_hio, v4, so * 4);
-      stv<ZV, AUX>(nl, r_loo, v4, so * 4);
-      stv<ZV, AUX>(om, r_om, v4, so * 4);
+      // st4 = kOob plus a plane offset below 2^31 stays out of range
+      const unsigned v4 = valid ? st4 + 4u * (unsigned)so : kOob;
+      stv<ZV, AUX>(nh, r_hio, v4);
+      stv<ZV, AUX>(nl, r_loo, v4);
+      stv<ZV, AUX>(om, r_om, v4);
       // past the chunk the computed bytes carry the held flag: never stored
       stb<ZV, AUX>(nlab, r_lab, (valid && nlab != P.b) ? st1 : kOob, so);
     }
@@ -323,18 +330,21 @@ static hipError_t launch_wide_ty(const TiledShape& s, Grid3 g, const StepBuffers
 
 template <int ZV, int TY>
 static hipError_t launch_wide_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
-                                 const StepConst& K, bool stream, hipStream_t st) {
-  return stream ? launch_wide_ty<ZV, TY, kStoreStream>(s, g, b, K, st)
-                : launch_wide_ty<ZV, TY, kStoreThrough>(s, g, b, K, st);
+                                 const StepConst& K, int store, hipStream_t st) {
+  switch (store) {
+    case kPolicyThrough: return launch_wide_ty<ZV, TY, kStoreThrough>(s, g, b, K, st);
+    case kPolicyStream: return launch_wide_ty<ZV, TY, kStoreStream>(s, g, b, K, st);
+    default: return launch_wide_ty<ZV, TY, kStoreBack>(s, g, b, K, st);
+  }
 }
 
 hipError_t launch_step_wide(int zv, const TiledShape& s, Grid3 g, const StepBuffers& b,
-                            const StepConst& K, bool stream, hipStream_t st) {
+                            const StepConst& K, int store, hipStream_t st) {
   if (!wide_fits(g, zv, s.xc)) return hipErrorInvalidValue;
-  if (zv == 4 && s.ty == 4) return launch_wide_ty<4, 4>(s, g, b, K, stream, st);
-  if (zv == 4 && s.ty == 8) return launch_wide_ty<4, 8>(s, g, b, K, stream, st);
-  if (zv == 2 && s.ty == 4) return launch_wide_ty<2, 4>(s, g, b, K, stream, st);
-  if (zv == 2 && s.ty == 8) return launch_wide_ty<2, 8>(s, g, b, K, stream, st);
+  if (zv == 4 && s.ty == 4) return launch_wide_ty<4, 4>(s, g, b, K, store, st);
+  if (zv == 4 && s.ty == 8) return launch_wide_ty<4, 8>(s, g, b, K, store, st);
+  if (zv == 2 && s.ty == 4) return launch_wide_ty<2, 4>(s, g, b, K, store, st);
+  if (zv == 2 && s.ty == 8) return launch_wide_ty<2, 8>(s, g, b, K, store, st);
   return hipErrorInvalidValue;
 }
 

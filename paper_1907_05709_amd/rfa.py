@@ -49,7 +49,7 @@ class rfa_options(C.Structure):
                 ("R", C.c_double), ("omega_cap", C.c_double), ("stream", C.c_void_p),
                 ("inputs_on_device", C.c_int), ("depth", C.c_int), ("kernel", C.c_int),
                 ("tile_y", C.c_int), ("tile_x", C.c_int), ("time_kernels", C.c_int),
-                ("z_vec", C.c_int)]
+                ("z_vec", C.c_int), ("store_policy", C.c_int)]
 
 
 class rfa_diag(C.Structure):
@@ -364,7 +364,7 @@ class Grid:
 
     def __init__(self, shape, spacing, device: bool = False, depth: int = 0,
                  stream=None, kernel: int = 0, tile_y: int = 0, tile_x: int = 0,
-                 time_kernels: int = 0, z_vec: int = 0, **damage):
+                 time_kernels: int = 0, z_vec: int = 0, store_policy: int = 0, **damage):
         self.shape = tuple(int(s) for s in shape)
         self.spacing = tuple(float(s) for s in spacing)
         self.device = bool(device)
@@ -378,6 +378,7 @@ class Grid:
         opt.tile_x = int(tile_x)
         opt.time_kernels = int(time_kernels)
         opt.z_vec = int(z_vec)
+        opt.store_policy = int(store_policy)
         if stream is not None:
             opt.stream = C.c_void_p(int(stream))
         elif self.device:
