@@ -55,17 +55,20 @@ struct Partial {
   unsigned mono;  // free voxels whose increment was negative
 };
 
-__device__ __forceinline__ float axis_term(float hi, float lo, float hm, float lm, float hp,
-                                           float lp, float2 cm, float2 cp) {
-  // The two faces of an axis are summed as a pair, products unfused, so that
-  // mirrored inputs give bitwise mirrored outputs.
-  const float dm = (hm - hi) + (lm - lo);
-  const float dp = (hp - hi) + (lp - lo);
-  return (cm.x * dm + cp.x * dp) + (cm.y * dm + cp.y * dp);
+// Float-float difference theta_nb - theta, rounded once.
+__device__ __forceinline__ float ff_diff(float hn, float ln, float hi, float lo) {
+  return (hn - hi) + (ln - lo);
 }
 
 // One voxel of one step.  Held voxels pass their own values as neighbours.
 // cf points at the LDS copy of Tables::cf (3 x 256 float2), cls at Tables::cls.
+//
+// The damage update has two forms with the same bits: branch-free (the
+// default, one basic block per plane, fewer live registers in the kernels
+// with one or two voxels per lane) and a select that lets the compiler
+// branch around the transcendentals off tissue (kSelectDamage, fewer live
+// registers where each lane carries four voxels).
+template <bool kSelectDamage = false>
 __device__ __forceinline__ void voxel_step(
     float hi, float lo, unsigned lab,
     float hxm, float lxm, unsigned bxm, float hxp, float lxp, unsigned bxp,
@@ -78,10 +81,27 @@ __device__ __forceinline__ void voxel_step(
   const float2* cx = cf + l * kMaxClasses;
   const float2* cy = cx + kMaxClasses * kMaxClasses;
   const float2* cz = cy + kMaxClasses * kMaxClasses;
-  const float ax = axis_term(hi, lo, hxm, lxm, hxp, lxp, cx[bxm & kClassMask], cx[bxp & kClassMask]);
-  const float ay = axis_term(hi, lo, hym, lym, hyp, lyp, cy[bym & kClassMask], cy[byp & kClassMask]);
-  const float az = axis_term(hi, lo, hzm, lzm, hzp, lzp, cz[bzm & kClassMask], cz[bzp & kClassMask]);
-  const float cond = (ax + ay) + az;
+  const float2 kxm = cx[bxm & kClassMask], kxp = cx[bxp & kClassMask];
+  const float2 kym = cy[bym & kClassMask], kyp = cy[byp & kClassMask];
+  const float2 kzm = cz[bzm & kClassMask], kzp = cz[bzp & kClassMask];
+  const float dxm = ff_diff(hxm, lxm, hi, lo), dxp = ff_diff(hxp, lxp, hi, lo);
+  const float dym = ff_diff(hym, lym, hi, lo), dyp = ff_diff(hyp, lyp, hi, lo);
+  const float dzm = ff_diff(hzm, lzm, hi, lo), dzp = ff_diff(hzp, lzp, hi, lo);
+  // Six face terms C(l, l_nb) d_nb, one fused chain per part of the
+  // float-float coefficient (the lo chain carries the coefficients'
+  // rounding, which is the same over a whole region).
+  float ch = kxm.x * dxm, cl = kxm.y * dxm;
+  ch = __builtin_fmaf(kxp.x, dxp, ch);
+  cl = __builtin_fmaf(kxp.y, dxp, cl);
+  ch = __builtin_fmaf(kym.x, dym, ch);
+  cl = __builtin_fmaf(kym.y, dym, cl);
+  ch = __builtin_fmaf(kyp.x, dyp, ch);
+  cl = __builtin_fmaf(kyp.y, dyp, cl);
+  ch = __builtin_fmaf(kzm.x, dzm, ch);
+  cl = __builtin_fmaf(kzm.y, dzm, cl);
+  ch = __builtin_fmaf(kzp.x, dzp, ch);
+  cl = __builtin_fmaf(kzp.y, dzp, cl);
+  const float cond = ch + cl;
   const float4 c = cls[l];
   const float bh = c.x * pf, bl = c.y * pf;
   const float perf = __builtin_fmaf(bh, hi, __builtin_fmaf(bl, hi, bh * lo));
@@ -101,8 +121,14 @@ __device__ __forceinline__ void voxel_step(
   x = fminf(x, K.clamp2);
   const float rate = K.dtka * __builtin_amdgcn_exp2f(x);
   const bool tissue = (lab & kTissue) != 0u;
-  om = tissue ? fminf(om + rate, K.cap) : om;
-  const bool reached = nh > K.thr || (nh == K.thr && nl >= 0.0f);
+  if constexpr (kSelectDamage) {
+    om = tissue ? fminf(om + rate, K.cap) : om;
+  } else {
+    // off tissue: om + rate * 0 = om and fminf(om, inf) = om (om >= +0)
+    om = fminf(__builtin_fmaf(rate, tissue ? 1.0f : 0.0f, om),
+               tissue ? K.cap : __builtin_huge_valf());
+  }
+  const bool reached = (nh > K.thr) | ((nh == K.thr) & (nl >= 0.0f));
   nlab = (tissue && reached) ? (lab | kLatch) : lab;
   acc.mono += (!held && inc < 0.0f) ? 1u : 0u;
   acc.perf = held ? acc.perf : __builtin_fmaf(c.w, perf, acc.perf);

@@ -121,8 +121,12 @@ struct WideSmem {
 
 }  // namespace
 
+// Two voxels per lane fit 128 VGPRs (four waves per SIMD) with a perfusion
+// field too, spilling only the partial sums around the plane loop; four
+// voxels per lane keep the compiler's choice (two waves per SIMD), since
+// three would spill inside the loop.
 template <int ZV, int TY, bool PERF, int AUX>
-__global__ __launch_bounds__(64 * TY) void k_step_wide(StepBuffers b, StepConst K, int nx,
+__global__ __launch_bounds__(64 * TY, ZV == 2 ? 4 : 1) void k_step_wide(StepBuffers b, StepConst K, int nx,
                                                        int ny, int nz, int xc, int tiles_z,
                                                        int tiles_y, int nwg) {
   static_assert(TY >= 3, "waves 0-2 load the halo");
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(64 * TY) void k_step_wide(StepBuffers b, StepConst 
       const float pf = PERF ? P.pf[k] : 1.0f;
       float h2, l2, o = om[k];
       unsigned lb2;
-      voxel_step(P.h[k], P.l[k], lab, hm[k], lm[k], byte_of(bm, k), N.h[k], N.l[k],
+      voxel_step<ZV == 4>(P.h[k], P.l[k], lab, hm[k], lm[k], byte_of(bm, k), N.h[k], N.l[k],
                  byte_of(N.b, k), hym[k], lym[k], byte_of(bym, k), hyp[k], lyp[k],
                  byte_of(byp, k), zmh, zml, zmb, zph, zpl, zpb, P.s[k], pf, o, sm.cf, sm.cls,
                  K, h2, l2, lb2, acc);
