@@ -135,14 +135,37 @@ __device__ __forceinline__ void voxel_step(
   acc.bnd = held ? acc.bnd : __builtin_fmaf(c.w, cond, acc.bnd);
 }
 
+// Wave sums through DPP lane moves instead of LDS permutes: lanes ^ 1 and
+// ^ 2 within quads, the half-row and row mirrors (every lane then holds its
+// 16-lane row's sum), then the GFX9 row broadcasts (lane 15 of rows 0 and
+// 2 added to rows 1 and 3, lane 31 to rows 2 and 3), which leave the total
+// in lane 63; it is read back to every lane.  Six dependent VALU steps
+// instead of six LDS round trips, in a fixed order.  Rows a move does not
+// write receive 0 (the old operand).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_move(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, kCtrl, kRowMask, 0xF, false);
+}
+
+template <typename T, typename Add>
+__device__ __forceinline__ T wave_sum_dpp(T v, Add add) {
+  auto bits = [](T x) { return __builtin_bit_cast(int, x); };
+  auto val = [](int x) { return __builtin_bit_cast(T, x); };
+  v = add(v, val(dpp_move<0xB1, 0xF>(bits(v))));   // quad_perm [1,0,3,2]
+  v = add(v, val(dpp_move<0x4E, 0xF>(bits(v))));   // quad_perm [2,3,0,1]
+  v = add(v, val(dpp_move<0x141, 0xF>(bits(v))));  // row_half_mirror
+  v = add(v, val(dpp_move<0x140, 0xF>(bits(v))));  // row_mirror
+  v = add(v, val(dpp_move<0x142, 0xA>(bits(v))));  // row_bcast:15 into rows 1, 3
+  v = add(v, val(dpp_move<0x143, 0xC>(bits(v))));  // row_bcast:31 into rows 2, 3
+  return val(__builtin_amdgcn_readlane(bits(v), 63));
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  return wave_sum_dpp(v, [](float a, float b) { return a + b; });
 }
 
 __device__ __forceinline__ unsigned wave_sum_u(unsigned v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  return wave_sum_dpp(v, [](unsigned a, unsigned b) { return a + b; });
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {

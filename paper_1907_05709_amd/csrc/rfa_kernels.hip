@@ -155,7 +155,28 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const float* partials,
   __shared__ double sh[3][16];
   const size_t n = (size_t)n_slots * nwg;
   double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-  for (size_t e = threadIdx.x; e < n; e += 1024) {
+  // Each thread sums elements threadIdx.x + 1024 k in increasing k; the
+  // loads of eight consecutive k are issued before their adds, so a
+  // launch costs a few memory latencies instead of one per element.
+  constexpr int kU = 8;
+  size_t e = threadIdx.x;
+  for (; e + (kU - 1) * 1024 < n; e += kU * 1024) {
+    float q[kU][3];
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      const float* p = partials + (e + (size_t)k * 1024) * 3;
+      q[k][0] = p[0];
+      q[k][1] = p[1];
+      q[k][2] = p[2];
+    }
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      v0 += (double)q[k][0];
+      v1 += (double)q[k][1];
+      v2 += (double)q[k][2];
+    }
+  }
+  for (; e < n; e += 1024) {
     const float* p = partials + e * 3;
     v0 += (double)p[0];
     v1 += (double)p[1];

@@ -176,5 +176,13 @@ def test_batch_rejects_unstable_dt_and_bad_args():
     with pytest.raises(rfa.RfaError) as e:
         rfa.Batch([grids[0], grids[0]], [cases[0].dt, cases[0].dt])
     assert e.value.status == rfa.RFA_ERR_ARG
+    b = rfa.Batch(grids, [c.dt for c in cases])
+    before = b.plan()
+    for bad in (dict(tile_y=6), dict(tile_x=-1), dict(workgroups=-2)):
+        with pytest.raises(rfa.RfaError) as e:
+            b.set_plan(**bad)
+        assert e.value.status == rfa.RFA_ERR_ARG
+    assert b.plan() == before
+    b.close()
     for g in grids:
         g.close()
