@@ -36,7 +36,7 @@ namespace {
 // out as Tables::cf, summed from its float-float parts.
 __device__ __forceinline__ float coef(const float2* cf, int axis, unsigned a, unsigned b) {
   const float2 c =
-      cf[axis * kMaxClasses * kMaxClasses + (a & kClassMask) * kMaxClasses + (b & kClassMask)];
+      cf[axis * kMaxClasses * kMaxClasses + class_of(a) * kMaxClasses + class_of(b)];
   return c.x + c.y;
 }
 
@@ -186,7 +186,7 @@ __device__ __forceinline__ bool adjoint_voxel(float lam, float th, unsigned lq, 
     lam_out = 0.0f;
     return false;
   }
-  const float4 cl = cls[lq & kClassMask];
+  const float4 cl = cls[class_of(lq)];
   const float B = (cl.x + cl.y) * pf;
   float diag = 1.0f - B;
   float off = 0.0f;
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(256) void k_source_dot(const uint8_t* lab, const Ch
        p += (size_t)gridDim.x * blockDim.x) {
     const unsigned v = lab[p];
     if (v & kHeld) continue;
-    const double sv = (double)sacc[p] * dt / cp->rc[v & kClassMask];
+    const double sv = (double)sacc[p] * dt / cp->rc[class_of(v)];
     if (sv == 0.0) continue;
     const int k = (int)(p % nz);
     const int j = (int)((p / nz) % ny);
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(256) void k_source_dot_fields(const uint8_t* lab, c
        p += (size_t)gridDim.x * blockDim.x) {
     const unsigned v = lab[p];
     if (v & kHeld) continue;
-    const double sv = (double)sacc[p] * dt / cp->rc[v & kClassMask];
+    const double sv = (double)sacc[p] * dt / cp->rc[class_of(v)];
     if (sv == 0.0) continue;
     acc += ut[p] * sv;
   }

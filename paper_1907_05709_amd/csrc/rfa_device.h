@@ -25,12 +25,19 @@
 
 namespace rfa {
 
-// Internal label byte: class in bits 0-3, flags above.
-constexpr unsigned kClassMask = 0x0Fu;
-constexpr unsigned kTissue = 0x10u;  // class accumulates damage
-constexpr unsigned kHeld = 0x40u;    // fixed class or outermost layer
-constexpr unsigned kLatch = 0x80u;   // t_death reached (sticky)
+// Internal label byte: class index in bits 3-6, flags in bits 0, 1 and 7.
+// With the class stored times 8, lab & kClassMask is the byte offset of the
+// class's float2 entry in a row of a coefficient table.
+constexpr unsigned kClassShift = 3;
+constexpr unsigned kClassMask = 0x78u;  // class << kClassShift
+constexpr unsigned kTissue = 0x01u;     // class accumulates damage
+constexpr unsigned kHeld = 0x02u;       // fixed class or outermost layer
+constexpr unsigned kLatch = 0x80u;      // t_death reached (sticky)
 constexpr int kMaxClasses = 16;
+
+__host__ __device__ constexpr unsigned class_of(unsigned lab) {
+  return (lab & kClassMask) >> kClassShift;
+}
 
 // Per-dt coefficient tables, staged into LDS by every work-group.
 struct Tables {
@@ -60,7 +67,10 @@ __device__ __forceinline__ float ff_diff(float hn, float ln, float hi, float lo)
   return (hn - hi) + (ln - lo);
 }
 
-// One voxel of one step.  Held voxels pass their own values as neighbours.
+// One voxel of one step.  No output of a held voxel depends on its
+// neighbours' values, which may be arbitrary (even NaN: the tiled kernels
+// leave halo cells outside the grid unwritten), so those values only ever
+// reach results through selects on the held flag.
 // cf points at the LDS copy of Tables::cf (3 x 256 float2), cls at Tables::cls.
 //
 // The damage update has two forms with the same bits: branch-free (the
@@ -77,13 +87,16 @@ __device__ __forceinline__ void voxel_step(
     float s, float pf, float& om, const float2* __restrict__ cf,
     const float4* __restrict__ cls, const StepConst& K,
     float& nh, float& nl, unsigned& nlab, Partial& acc) {
-  const unsigned l = lab & kClassMask;
-  const float2* cx = cf + l * kMaxClasses;
-  const float2* cy = cx + kMaxClasses * kMaxClasses;
-  const float2* cz = cy + kMaxClasses * kMaxClasses;
-  const float2 kxm = cx[bxm & kClassMask], kxp = cx[bxp & kClassMask];
-  const float2 kym = cy[bym & kClassMask], kyp = cy[byp & kClassMask];
-  const float2 kzm = cz[bzm & kClassMask], kzp = cz[bzp & kClassMask];
+  // C(l, l_nb) addressed in bytes: row of the own class (16 entries of 8
+  // bytes), entry of the neighbour's class (its masked label byte)
+  const unsigned row = (lab & kClassMask) << 4;
+  auto entry = [&](int axis, unsigned nb) {
+    const char* t = reinterpret_cast<const char*>(cf + axis * kMaxClasses * kMaxClasses);
+    return *reinterpret_cast<const float2*>(t + (row | (nb & kClassMask)));
+  };
+  const float2 kxm = entry(0, bxm), kxp = entry(0, bxp);
+  const float2 kym = entry(1, bym), kyp = entry(1, byp);
+  const float2 kzm = entry(2, bzm), kzp = entry(2, bzp);
   const float dxm = ff_diff(hxm, lxm, hi, lo), dxp = ff_diff(hxp, lxp, hi, lo);
   const float dym = ff_diff(hym, lym, hi, lo), dyp = ff_diff(hyp, lyp, hi, lo);
   const float dzm = ff_diff(hzm, lzm, hi, lo), dzp = ff_diff(hzp, lzp, hi, lo);
@@ -102,7 +115,7 @@ __device__ __forceinline__ void voxel_step(
   ch = __builtin_fmaf(kzp.x, dzp, ch);
   cl = __builtin_fmaf(kzp.y, dzp, cl);
   const float cond = ch + cl;
-  const float4 c = cls[l];
+  const float4 c = cls[class_of(lab)];
   const float bh = c.x * pf, bl = c.y * pf;
   const float perf = __builtin_fmaf(bh, hi, __builtin_fmaf(bl, hi, bh * lo));
   const float inc = (cond - perf) + (c.z + s);

@@ -262,7 +262,7 @@ __global__ void k_build_labels(const uint8_t* user, uint8_t* lab, const ClassPar
       lab[p] = 0;
       continue;
     }
-    unsigned v = u;
+    unsigned v = u << kClassShift;
     if (cp->tissue[u]) v |= kTissue;
     const bool outer = i == 0 || j == 0 || k == 0 || i == nx - 1 || j == ny - 1 || k == nz - 1;
     if (cp->fixed[u] || outer) v |= kHeld;
@@ -291,7 +291,7 @@ __global__ void k_reset_state(uint8_t* lab, float* hi, float* lo, float* om, con
   for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
        p += (size_t)gridDim.x * blockDim.x) {
     unsigned v = lab[p] & ~kLatch;
-    const unsigned c = v & kClassMask;
+    const unsigned c = class_of(v);
     const double th = cp->fixed[c] ? cp->t_fixed[c] - 37.0 : 0.0;
     float h, l;
     split_theta(th, h, l);
@@ -327,12 +327,12 @@ __global__ __launch_bounds__(kRedThreads) void k_dt_bound(const uint8_t* lab, co
        p += (size_t)gridDim.x * blockDim.x) {
     const unsigned v = lab[p];
     if (v & kHeld) continue;
-    const unsigned c = v & kClassMask;
+    const unsigned c = class_of(v);
     const size_t sx = (size_t)ny * nz, sy = nz;
     double s = cp->h[c] * (perf ? (double)perf[p] : 1.0);
-    s += (face_k(cp, c, lab[p - sx] & kClassMask) + face_k(cp, c, lab[p + sx] & kClassMask)) * ix;
-    s += (face_k(cp, c, lab[p - sy] & kClassMask) + face_k(cp, c, lab[p + sy] & kClassMask)) * iy;
-    s += (face_k(cp, c, lab[p - 1] & kClassMask) + face_k(cp, c, lab[p + 1] & kClassMask)) * iz;
+    s += (face_k(cp, c, class_of(lab[p - sx])) + face_k(cp, c, class_of(lab[p + sx]))) * ix;
+    s += (face_k(cp, c, class_of(lab[p - sy])) + face_k(cp, c, class_of(lab[p + sy]))) * iy;
+    s += (face_k(cp, c, class_of(lab[p - 1])) + face_k(cp, c, class_of(lab[p + 1]))) * iz;
     const double d = s > 0.0 ? cp->rc[c] / s : INFINITY;
     best = fmin(best, d);
   }
@@ -531,7 +531,7 @@ __global__ void k_source_increment(const uint8_t* lab, const double* q, const Cl
   for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
        p += (size_t)gridDim.x * blockDim.x) {
     const unsigned v = lab[p];
-    s[p] = (v & kHeld) ? 0.0f : (float)(dt * q[p] / cp->rc[v & kClassMask]);
+    s[p] = (v & kHeld) ? 0.0f : (float)(dt * q[p] / cp->rc[class_of(v)]);
   }
 }
 
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(kRedThreads) void k_state_reduce(const uint8_t* lab
       continue;
     }
     const unsigned v = lab[p];
-    if (!(v & kHeld)) e += cp->rc[v & kClassMask] * th;
+    if (!(v & kHeld)) e += cp->rc[class_of(v)] * th;
     mn = fmin(mn, th);
     mx = fmax(mx, th);
   }
@@ -619,8 +619,8 @@ __global__ __launch_bounds__(256) void k_damage(const uint8_t* lab, const float*
     const unsigned b0 = (tis && (v & kLatch)) ? 1u : 0u;
     const unsigned b1 = (tis && om[p] >= 1.0f) ? 2u : 0u;
     if (mask) mask[p] = (uint8_t)(b0 | b1);
-    if (b0) atomicAdd(&cnt[v & kClassMask][0], 1u);
-    if (b1) atomicAdd(&cnt[v & kClassMask][1], 1u);
+    if (b0) atomicAdd(&cnt[class_of(v)][0], 1u);
+    if (b1) atomicAdd(&cnt[class_of(v)][1], 1u);
   }
   __syncthreads();
   if (threadIdx.x < 2 * kMaxClasses) {
@@ -684,7 +684,7 @@ __global__ __launch_bounds__(256) void k_free_counts(const uint8_t* lab,
   for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
        p += (size_t)gridDim.x * blockDim.x) {
     const unsigned v = lab[p];
-    if (!(v & kHeld)) atomicAdd(&cnt[v & kClassMask], 1u);
+    if (!(v & kHeld)) atomicAdd(&cnt[class_of(v)], 1u);
   }
   __syncthreads();
   if (threadIdx.x < kMaxClasses && cnt[threadIdx.x])

@@ -199,7 +199,7 @@ __device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& 
     float nh, nl, om = P.om;
     unsigned nlab;
     const bool valid = x < c.x1;                        // uniform
-    const unsigned lab = valid ? P.b : (P.b | kHeld);   // past the chunk: no contributions
+    const unsigned lab = P.b | (valid ? 0u : kHeld);   // past the chunk: no contributions
     voxel_step(P.h, P.l, lab, hm, lm, bm, N.h, N.l, N.b, ym.x, ym.y, bym, yp.x, yp.y, byp,
                zm.x, zm.y, bzm, zp.x, zp.y, bzp, P.s, P.pf, om, sm.cf, sm.cls, K, nh, nl, nlab,
                acc);

@@ -248,12 +248,14 @@ __global__ __launch_bounds__(64 * TY, ZV == 2 ? 4 : 1) void k_step_wide(StepBuff
     const unsigned bzm = sm.tb[BUF][me - 1], bzp = sm.tb[BUF][me + ZV];
     const PlaneW<ZV>& N = q[SN];
     const bool valid = x < x1;  // uniform
+    // past the chunk every voxel is computed as held: no contributions
+    const unsigned held_all = valid ? 0u : kHeld * (ZV == 4 ? 0x01010101u : 0x0101u);
+    const unsigned pb = P.b | held_all;
     VF nh, nl, om = P.om;
     unsigned nlab = 0u;
 #pragma unroll
     for (int k = 0; k < ZV; ++k) {
-      const unsigned bk = byte_of(P.b, k);
-      const unsigned lab = valid ? bk : (bk | kHeld);  // past the chunk: no contributions
+      const unsigned lab = byte_of(pb, k);
       const float zmh = k > 0 ? P.h[k > 0 ? k - 1 : 0] : hzm;
       const float zml = k > 0 ? P.l[k > 0 ? k - 1 : 0] : lzm;
       const unsigned zmb = k > 0 ? byte_of(P.b, k > 0 ? k - 1 : 0) : bzm;
@@ -270,7 +272,7 @@ __global__ __launch_bounds__(64 * TY, ZV == 2 ? 4 : 1) void k_step_wide(StepBuff
       nh[k] = h2;
       nl[k] = l2;
       om[k] = o;
-      nlab |= (lb2 & 0xFFu) << (8 * k);
+      nlab |= lb2 << (8 * k);  // lab plus the latch bit: one byte
     }
     {
       const int so = (min(x, x1 - 1) - xb) * (int)psz;  // uniform
