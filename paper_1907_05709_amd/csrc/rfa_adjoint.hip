@@ -32,14 +32,6 @@ namespace rfa {
 
 namespace {
 
-// Conduction coefficient C(a, b) along an axis from a coefficient table laid
-// out as Tables::cf, summed from its float-float parts.
-__device__ __forceinline__ float coef(const float2* cf, int axis, unsigned a, unsigned b) {
-  const float2 c =
-      cf[axis * kMaxClasses * kMaxClasses + class_of(a) * kMaxClasses + class_of(b)];
-  return c.x + c.y;
-}
-
 __device__ double block_sum_256(double v, double* sh) {
   v = wave_sum_d(v);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -175,6 +167,9 @@ hipError_t launch_adjoint_weight(Grid3 g, const float* w, const float* om, const
 // a free voxel; a held voxel gets lam_out = 0 and accumulates nothing
 // (returns false).  Neighbours in the order x-, x+, y-, y+, z-, z+; cf and
 // cls point at the coefficient tables (global or LDS copy, same layout).
+// Branch-free: a held voxel's neighbour values may be arbitrary (the tiled
+// kernel leaves halo cells outside the grid unwritten) and reach nothing
+// but selects on the held flags.
 __device__ __forceinline__ bool adjoint_voxel(float lam, float th, unsigned lq, float pf,
                                               float w, const float (&nlam)[6],
                                               const unsigned (&nlab)[6],
@@ -182,34 +177,39 @@ __device__ __forceinline__ bool adjoint_voxel(float lam, float th, unsigned lq, 
                                               const float4* __restrict__ cls,
                                               const StepConst& K, float& lam_out,
                                               float& sacc, float& facc) {
-  if (lq & kHeld) {
-    lam_out = 0.0f;
-    return false;
-  }
+  const bool held = (lq & kHeld) != 0u;
   const float4 cl = cls[class_of(lq)];
   const float B = (cl.x + cl.y) * pf;
+  // table entries in bytes: row of a class = its masked label << 4, entry =
+  // the other class's masked label (the label keeps the class times 8)
+  const unsigned cq = lq & kClassMask;
+  auto c_at = [&](int axis, unsigned byte_off) {
+    const char* t = reinterpret_cast<const char*>(cf + axis * kMaxClasses * kMaxClasses);
+    const float2 c = *reinterpret_cast<const float2*>(t + byte_off);
+    return c.x + c.y;
+  };
   float diag = 1.0f - B;
   float off = 0.0f;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     const unsigned lp = nlab[f];
-    diag -= coef(cf, f >> 1, lq, lp);                  // q's own row
-    if (!(lp & kHeld)) off = __builtin_fmaf(coef(cf, f >> 1, lp, lq), nlam[f], off);
+    const unsigned cp = lp & kClassMask;
+    diag -= c_at(f >> 1, (cq << 4) | cp);                          // C(q, p): q's own row
+    const float o = __builtin_fmaf(c_at(f >> 1, (cp << 4) | cq), nlam[f], off);  // C(p, q)
+    off = (lp & kHeld) ? off : o;
   }
-  // damage-rate derivative at theta^n (zero where the exponent is capped)
-  float dr = 0.0f;
-  if (lq & kTissue) {
-    const float tk = K.tak + th;
-    const float x = K.c2 * th / tk;
-    if (x < K.clamp2) {
-      const float rate = K.dtka * __builtin_amdgcn_exp2f(x);
-      dr = rate * (K.c2 * 0.69314718f) * K.tak / (tk * tk);
-    }
-  }
-  lam_out = __builtin_fmaf(diag, lam, off) + w * dr;
-  sacc += lam;
-  facc = __builtin_fmaf(-cl.x - cl.y, th * lam, facc);
-  return true;
+  // damage-rate derivative at theta^n, the rate evaluated as the forward
+  // step evaluates it (zero off tissue and where the exponent is capped)
+  const float r = __builtin_amdgcn_rcpf(K.tak + th);
+  const float x = K.c2 * th * r;
+  const float rate = K.dtka * __builtin_amdgcn_exp2f(fminf(x, K.clamp2));
+  const float dr0 = rate * (K.c2 * 0.69314718f) * K.tak * (r * r);
+  const float dr = ((lq & kTissue) != 0u && x < K.clamp2) ? dr0 : 0.0f;
+  const float lo = __builtin_fmaf(diag, lam, off) + w * dr;
+  lam_out = held ? 0.0f : lo;
+  sacc = held ? sacc : sacc + lam;
+  facc = held ? facc : __builtin_fmaf(-cl.x - cl.y, th * lam, facc);
+  return !held;
 }
 
 // Reference adjoint step, one thread per voxel.
