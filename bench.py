@@ -311,6 +311,7 @@ def bench_adjoint(args):
     g = rfa.Grid(case.shape, case.spacing, device=True, time_kernels=TIME_PERIOD)
     g.load_case(case)
     g.set_perfusion_bspline(np.zeros((m, m, m), np.float32))
+    plan = g.plan()
     labels = torch.from_numpy(case.labels).cuda()
     vox = float(np.prod(case.spacing))
 
@@ -358,7 +359,7 @@ def bench_adjoint(args):
                    "loss": loss, "dL_dP": [float(x) for x in dP]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": None, "kernel": "k_step_tiled (forward and recompute)",
+                     "traffic": None, "kernel": kernel_name(plan) + " (forward and recompute)",
                      "avg_launch_us": round(avg_ms * 1e3, 3),
                      "bytes_per_launch": bytes_per_launch},
     }

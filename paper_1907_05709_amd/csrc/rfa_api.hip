@@ -130,7 +130,6 @@ struct rfa_grid_s {
   bool energy_valid = false;
 
   StepPlan plan{};
-  bool plan_tuned = false;
 
   // step-kernel timing
   std::vector<hipEvent_t> events;
@@ -239,14 +238,6 @@ StepConst step_const(rfa_grid g, double dt) {
   K.cap = (float)g->opt.omega_cap;
   K.thr = (float)(g->opt.t_death - 37.0);
   return K;
-}
-
-// Re-derive an automatic launch plan after the perfusion field came or went
-// (a plan from rfa_tune or explicit options stays).
-void refresh_plan(rfa_grid g) {
-  if (g->plan_tuned) return;
-  g->plan = plan_default(g->g, g->opt.kernel, g->opt.depth, g->opt.tile_y, g->opt.tile_x,
-                         g->opt.z_vec, g->perf != nullptr, g->opt.store_policy);
 }
 
 rfa_status compute_dt_max(rfa_grid g) {
@@ -572,8 +563,7 @@ rfa_status rfa_create_grid(int nx, int ny, int nz, double dx, double dy, double 
     return fail(RFA_ERR_HIP, "no HIP device");
   }
   const size_t n = g->g.n();
-  g->plan = plan_default(g->g, o.kernel, o.depth, o.tile_y, o.tile_x, o.z_vec, false,
-                         o.store_policy);
+  g->plan = plan_default(g->g, o.kernel, o.depth, o.tile_y, o.tile_x, o.z_vec, o.store_policy);
   const size_t nwg = (size_t)plan_max_wg(g->g);
   g->partial_floats = nwg * 3 * kPartialSlots;
   g->red_doubles = 4 * 1024 + 64;
@@ -736,7 +726,6 @@ rfa_status rfa_set_perfusion(rfa_grid g, const float* factor) {
   if (!factor) {
     if (g->perf) (void)hipFree(g->perf);
     g->perf = nullptr;
-    refresh_plan(g);
     return compute_dt_max(g);
   }
   if (!g->opt.inputs_on_device) {
@@ -749,7 +738,6 @@ rfa_status rfa_set_perfusion(rfa_grid g, const float* factor) {
     if (s != RFA_OK) return s;
   }
   HIP_TRY(hipMemcpyAsync(g->perf, factor, n * sizeof(float), kind_in(g), g->st));
-  refresh_plan(g);
   return compute_dt_max(g);
 }
 
@@ -1022,7 +1010,6 @@ rfa_status rfa_tune(rfa_grid g, double dt, int reps) {
   for (auto& kv : g_tuned)
     if (kv.first == key) {
       g->plan = kv.second;
-      g->plan_tuned = true;
       return RFA_OK;
     }
   if (dt != g->tab_dt) {
@@ -1084,7 +1071,6 @@ rfa_status rfa_tune(rfa_grid g, double dt, int reps) {
   (void)hipFree(lab2);
   if (e != hipSuccess) return fail(RFA_ERR_HIP, "tune failed: %s", hipGetErrorString(e));
   g->plan = best;
-  g->plan_tuned = true;
   g_tuned.push_back({key, best});
   return RFA_OK;
 }
@@ -1169,7 +1155,6 @@ rfa_status rfa_set_perfusion_bspline(rfa_grid g, int m, const float* ctrl) {
   HIP_TRY(hipStreamSynchronize(g->st));
   g->bs_m = m;
   ++g->version;
-  refresh_plan(g);
   return compute_dt_max(g);
 }
 

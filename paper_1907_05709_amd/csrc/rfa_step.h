@@ -34,10 +34,9 @@ StepPlan plan_wide(Grid3 g, int zv, int ty, int xc);
 // The one-step plan that accompanies a plan.
 StepPlan plan_one(const StepPlan& p);
 // Heuristic plan from the options (kernel, depth, tile_y, tile_x, z_vec,
-// store = 1 + StorePolicy; 0 = automatic); perf: the grid carries a
-// perfusion field.
+// store = 1 + StorePolicy; 0 = automatic).
 StepPlan plan_default(Grid3 g, int kernel, int depth, int tile_y, int tile_x, int zv,
-                      bool perf = false, int store = 0);
+                      int store = 0);
 // Candidate plans for tuning (depth 1, and depth 2 if max_depth >= 2).
 int plan_candidates(Grid3 g, int max_depth, StepPlan* out, int max_out);
 // Largest partial stride any plan of this grid can need.

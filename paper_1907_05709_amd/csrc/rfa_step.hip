@@ -106,14 +106,12 @@ StepPlan plan_one(const StepPlan& p) {
 }
 
 namespace {
-StepPlan default_shape(Grid3 g, int kernel, int depth, int tile_y, int tile_x, int zv,
-                       bool perf) {
+StepPlan default_shape(Grid3 g, int kernel, int depth, int tile_y, int tile_x, int zv) {
   if (kernel == kStepNaive || !tiled_fits(g, 4)) return plan_naive(g);
   // automatic: four z voxels per lane once a tile row spans 256 voxels, two
-  // (with 8-row tiles) from 96 without a perfusion field (with one, the
-  // extra vector stream makes one voxel per lane faster at these sizes)
+  // (with 8-row tiles) from 96
   if (zv == 0 && depth != 2 && g.nz >= 256 && g.nz % 4 == 0) zv = 4;
-  if (zv == 0 && depth != 2 && !perf && g.nz >= 96 && g.nz % 2 == 0) zv = 2;
+  if (zv == 0 && depth != 2 && g.nz >= 96 && g.nz % 2 == 0) zv = 2;
   if (depth != 2 && (zv == 2 || zv == 4) && wide_fits(g, zv, 4) && tile_y != 16) {
     const int ty = tile_y ? tile_y : (zv == 2 ? 8 : 4);
     const int tiles = ((g.nz + 64 * zv - 1) / (64 * zv)) * ((g.ny + ty - 1) / ty);
@@ -138,8 +136,8 @@ StepPlan default_shape(Grid3 g, int kernel, int depth, int tile_y, int tile_x, i
 }  // namespace
 
 StepPlan plan_default(Grid3 g, int kernel, int depth, int tile_y, int tile_x, int zv,
-                      bool perf, int store) {
-  StepPlan p = default_shape(g, kernel, depth, tile_y, tile_x, zv, perf);
+                      int store) {
+  StepPlan p = default_shape(g, kernel, depth, tile_y, tile_x, zv);
   if (store > 0 && p.kind != kStepNaive) p.store = store - 1;
   return p;
 }
