@@ -281,12 +281,12 @@ def bench_batch(args):
                    "batched_speedup_vs_plain": round(value / seq_value, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": None, "kernel": "k_step_batch",
+                     "traffic": traffic_record(4, plan), "kernel": "k_step_batch",
                      "avg_launch_us": round(avg_launch_ms * 1e3, 3),
                      "bytes_per_launch": round(bytes_per_launch),
                      "note": "groups of grids sized to the 256 MB last-level cache run "
-                             "their steps back to back, so much of this traffic is served "
-                             "by that cache rather than HBM"},
+                             "their steps back to back; traffic counts bytes below L2, "
+                             "which that cache may serve"},
     }
     print(json.dumps(out), flush=True)
 
