@@ -266,8 +266,8 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
  * grids are grouped up to a voxel budget (by default 8 Mi voxels, whose
  * stepping working set fits the 256 MB last-level cache); a group runs
  * all its steps before the next group starts, one kernel launch per step
- * over the concatenated tile lists of its grids (two when some grids carry a
- * perfusion field and others do not).  The whole launch sequence of an
+ * over the concatenated work-item lists of its grids (two when some grids
+ * carry a perfusion field and others do not).  The whole launch sequence of an
  * rfa_batch_step call is captured once in a hipGraph and replayed on later
  * calls with the same step count.  The per-voxel
  * arithmetic is that of rfa_step (Eq. (CUDAbioheat3d), Alg. 1 and 2), so a
@@ -287,18 +287,31 @@ rfa_status rfa_batch_create(int n, const rfa_grid* grids, const double* dt, rfa_
  * call then synchronises). */
 rfa_status rfa_batch_step(rfa_batch b, int n_steps, rfa_diag* diags);
 
-/* Launch shape of the batch kernel: tile_y (4 or 8) rows per work-group,
- * tile_x planes per work item, workgroups > 0 persistent work-groups per
- * launch that walk the work list (0, the default: one work-group per work
- * item), group_voxels the grouping budget (0: all grids in one group, i.e.
- * lockstep; < 0: keep the current one).  Zero tile values keep the
- * automatic choice.  Drops cached graphs. */
-rfa_status rfa_batch_set_plan(rfa_batch b, int tile_y, int tile_x, int workgroups,
+/* Work-item layouts of the batch kernel. */
+enum {
+  RFA_BATCH_TILES = 1, /* 2.5-D tiles: 64 z voxels by tile_y rows */
+  RFA_BATCH_FLAT = 2   /* flat segments of 64 * tile_y consecutive voxels of a
+                          (y, z) plane; needs nz <= 32 * tile_y in every grid */
+};
+
+/* Launch shape of the batch kernel (default: RFA_BATCH_FLAT with 8 waves
+ * when every grid has nz <= 256, else RFA_BATCH_TILES with 4 rows; 8 x
+ * planes per work item; groups of at most 8 Mi voxels): layout (0: keep,
+ * else RFA_BATCH_*),
+ * tile_y waves per work-group (tiles: 4 or 8 rows; flat: 8 or 16; 0 keeps
+ * the current value, or takes 4 / 8 when the layout changes), tile_x
+ * planes per work item, workgroups > 0 persistent work-groups per launch
+ * that walk the work list (0, the default: one work-group per work item),
+ * group_voxels the grouping budget (0: all grids in one group, i.e.
+ * lockstep; < 0: keep the current one).  On error the plan is unchanged.
+ * Drops cached graphs. */
+rfa_status rfa_batch_set_plan(rfa_batch b, int layout, int tile_y, int tile_x, int workgroups,
                               long long group_voxels);
 
-/* Current launch shape: tile_y, tile_x, work items per step (all groups),
- * work-groups launched per step of all grids, number of groups. */
-rfa_status rfa_batch_get_plan(rfa_batch b, int* tile_y, int* tile_x, int* items,
+/* Current launch shape: layout, tile_y, tile_x, work items per step (all
+ * groups), work-groups launched per step of all grids, number of groups
+ * (each pointer nullable). */
+rfa_status rfa_batch_get_plan(rfa_batch b, int* layout, int* tile_y, int* tile_x, int* items,
                               int* workgroups, int* groups);
 
 /* Device time of the last rfa_batch_step's graph, milliseconds (HIP events

@@ -1394,6 +1394,7 @@ struct rfa_batch_s {
   int n_items = 0;
   int ty = 4;
   int xc = 8;
+  bool flat = false;                // items are flat plane segments (else 2.5-D tiles)
   int n_wg = 0;
   int req_wg = 0;                   // persistent work-groups (0: one per item)
   long long group_budget = kBatchGroupVoxels;  // voxels per group (0: one group)
@@ -1472,6 +1473,9 @@ rfa_status batch_build(rfa_batch b) {
     I.nz = g->g.nz;
     I.xc = std::min(b->xc, g->g.nx);
     if (!tiled_fits(g->g, I.xc)) return fail(RFA_ERR_ARG, "grid %d too large for a batch", i);
+    if (b->flat && g->g.nz > flat_max_nz(b->ty))
+      return fail(RFA_ERR_ARG, "grid %d: nz = %d exceeds %d for flat items of %d waves", i,
+                  g->g.nz, flat_max_nz(b->ty), b->ty);
     b->voxels += (long long)g->g.n();
   }
   // Groups of consecutive grids up to the voxel budget; a group runs all its
@@ -1493,7 +1497,8 @@ rfa_status batch_build(rfa_batch b) {
       for (int i = i0; i < i1; ++i) {
         const BatchInstance& I = b->inst[i];
         if ((I.perf != nullptr) != (pass == 1)) continue;
-        const TiledShape sh = tiled_shape(b->grids[i]->g, b->ty, I.xc);
+        const TiledShape sh = b->flat ? flat_shape(b->grids[i]->g, b->ty, I.xc)
+                                      : tiled_shape(b->grids[i]->g, b->ty, I.xc);
         b->first[2 * i] = (int)items.size();
         for (int tx = 0; tx < sh.chunks_x; ++tx)
           for (int ty = 0; ty < sh.tiles_y; ++ty)
@@ -1561,11 +1566,11 @@ rfa_status batch_graph(rfa_batch b, int n_steps, bool diag, hipGraphExec_t* out)
     for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
       float* part = diag ? b->partials + (size_t)pending * b->n_items * 3 : nullptr;
       const int par = (b->parity + s) & 1;
-      e = launch_step_batch(b->ty, false, b->inst_dev, b->items_dev, G.plain0, n_plain,
-                            wg_plain, par, part, b->st);
+      e = launch_step_batch(b->ty, b->flat, false, b->inst_dev, b->items_dev, G.plain0,
+                            n_plain, wg_plain, par, part, b->st);
       if (e == hipSuccess)
-        e = launch_step_batch(b->ty, true, b->inst_dev, b->items_dev, G.perf0, n_perf, wg_perf,
-                              par, part, b->st);
+        e = launch_step_batch(b->ty, b->flat, true, b->inst_dev, b->items_dev, G.perf0, n_perf,
+                              wg_perf, par, part, b->st);
       if (e == hipSuccess && diag && ++pending == kPartialSlots) {
         e = launch_reduce_batch(b->partials, pending, b->n_items, b->first_dev, G.inst0,
                                 G.inst1 - G.inst0, b->dacc, b->st);
@@ -1618,6 +1623,11 @@ rfa_status rfa_batch_create(int n, const rfa_grid* grids, const double* dt, rfa_
   if (!b) return fail(RFA_ERR_OOM, "host allocation failed");
   b->grids.assign(grids, grids + n);
   b->dt.assign(dt, dt + n);
+  // default layout: flat plane segments of 8 waves (no lanes lost to rows
+  // shorter than a multiple of 64) where every grid allows them
+  b->flat = true;
+  for (int i = 0; i < n; ++i) b->flat = b->flat && grids[i]->g.nz <= flat_max_nz(8);
+  b->ty = b->flat ? 8 : 4;
   hipError_t e = hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreate(&b->ev0);
   if (e == hipSuccess) e = hipEventCreate(&b->ev1);
@@ -1689,22 +1699,42 @@ rfa_status rfa_batch_step(rfa_batch b, int n_steps, rfa_diag* diags) {
   return RFA_OK;
 }
 
-rfa_status rfa_batch_set_plan(rfa_batch b, int tile_y, int tile_x, int workgroups,
+rfa_status rfa_batch_set_plan(rfa_batch b, int layout, int tile_y, int tile_x, int workgroups,
                               long long group_voxels) {
   if (!b) return fail(RFA_ERR_ARG, "batch is NULL");
-  if (tile_y != 0 && tile_y != 4 && tile_y != 8) return fail(RFA_ERR_ARG, "tile_y: 0, 4 or 8");
+  if (layout < 0 || layout > RFA_BATCH_FLAT) return fail(RFA_ERR_ARG, "layout: 0, 1 or 2");
+  const bool flat = layout ? layout == RFA_BATCH_FLAT : b->flat;
+  const int ty = tile_y ? tile_y : (flat == b->flat ? b->ty : (flat ? 8 : 4));
+  if (!flat && ty != 4 && ty != 8) return fail(RFA_ERR_ARG, "tile_y of 2.5-D tiles: 4 or 8");
+  if (flat && ty != 8 && ty != 16) return fail(RFA_ERR_ARG, "tile_y of flat items: 8 or 16");
   if (tile_x < 0 || workgroups < 0) return fail(RFA_ERR_ARG, "tile_x, workgroups >= 0");
   if (b->st) HIP_TRY(hipStreamSynchronize(b->st));
-  if (tile_y) b->ty = tile_y;
+  const bool flat0 = b->flat;
+  const int ty0 = b->ty, xc0 = b->xc, wg0 = b->req_wg;
+  const long long gv0 = b->group_budget;
+  b->flat = flat;
+  b->ty = ty;
   if (tile_x) b->xc = tile_x;
   b->req_wg = workgroups;
   if (group_voxels >= 0) b->group_budget = group_voxels;
-  return batch_build(b);
+  rfa_status s = batch_build(b);
+  if (s != RFA_OK) {  // keep the previous plan
+    std::string err = g_last_error;
+    b->flat = flat0;
+    b->ty = ty0;
+    b->xc = xc0;
+    b->req_wg = wg0;
+    b->group_budget = gv0;
+    (void)batch_build(b);
+    g_last_error = err;
+  }
+  return s;
 }
 
-rfa_status rfa_batch_get_plan(rfa_batch b, int* tile_y, int* tile_x, int* items,
+rfa_status rfa_batch_get_plan(rfa_batch b, int* layout, int* tile_y, int* tile_x, int* items,
                               int* workgroups, int* groups) {
   if (!b) return fail(RFA_ERR_ARG, "batch is NULL");
+  if (layout) *layout = b->flat ? RFA_BATCH_FLAT : RFA_BATCH_TILES;
   if (tile_y) *tile_y = b->ty;
   if (tile_x) *tile_x = b->xc;
   if (items) *items = b->n_items;

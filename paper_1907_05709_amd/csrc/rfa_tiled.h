@@ -42,13 +42,19 @@ struct BatchItem {
 // One step of the items [first_item, first_item + n_items) of a batch, all
 // of instances with (perf) or without a perfusion field: n_wg > 0 persistent
 // work-groups of 64*ty threads walk the items, n_wg == 0 launches one
-// work-group per item.  partials (nullable) receives 3 floats per item,
-// indexed by item.
-hipError_t launch_step_batch(int ty, bool perf, const BatchInstance* inst,
+// work-group per item.  Items are 2.5-D tiles of tiled_shape (ty = 4 or 8)
+// or, with flat, plane segments of flat_shape (ty = 8 or 16 waves, grids
+// with nz <= flat_max_nz(ty)).  partials (nullable) receives 3 floats per
+// item, indexed by item.
+hipError_t launch_step_batch(int ty, bool flat, bool perf, const BatchInstance* inst,
                              const BatchItem* items, int first_item, int n_items, int n_wg,
                              int parity, float* partials, hipStream_t st);
 
 TiledShape tiled_shape(Grid3 g, int ty, int xc);
+// Flat plane segments of 64 ty voxels (tiles_z = segments per plane,
+// tiles_y = 1) and the largest nz they support.
+TiledShape flat_shape(Grid3 g, int ty, int xc);
+int flat_max_nz(int ty);
 // Whether a chunk of xc planes fits the kernel's 32-bit plane offsets.
 bool tiled_fits(Grid3 g, int xc);
 // store: StorePolicy of the launch's stores.

@@ -90,7 +90,7 @@ __device__ __forceinline__ void load_plane(const TileCtx& c, int x, bool perf, P
 
 
 
-// LDS working set of one work-group.
+// LDS working set of one work-group (2.5-D tile: 64 z by TY rows).
 template <int TY>
 struct TileSmem {
   static constexpr int W = 66;            // 64 lanes + z halo
@@ -103,15 +103,37 @@ struct TileSmem {
   float red[3][TY];
 };
 
-// March one tile (tz, ty) over the x-chunk [tx*xc, tx*xc + xc) of one grid.
-// Tables must be staged (a barrier inside the march orders them).  The
-// work-group's partial sums are written to partials[wg_slot * 3] if
-// partials is not null.
-template <int TY, int AUX>
-__device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& b,
-                                           const StepConst& K, bool perf, int nx, int ny,
-                                           int nz, int xc, int tz, int ty, int tx,
-                                           float* partials, int wg_slot) {
+// LDS working set of a flat work-group: T = 64 NW consecutive voxels of a
+// plane in (y, z) order, plus nz voxels before and after them (the y
+// neighbours); grids up to nz = T / 2.
+template <int NW>
+struct FlatSmem {
+  static constexpr int T = 64 * NW;
+  static constexpr int MAX_NZ = T / 2;
+  static constexpr int CELLS = T + 2 * MAX_NZ;  // plus one scratch cell
+  float2 cf[3 * kMaxClasses * kMaxClasses];
+  float4 cls[kMaxClasses];
+  float2 ts[2][CELLS + 1];
+  uint8_t bs[2][CELLS + 1];
+  float red[3][NW];
+};
+
+// Where one thread sits in its work-group's LDS plane.
+struct LanePlace {
+  unsigned col;   // own column offset (voxels) in a plane; 0 outside the grid
+  bool inside;    // own column inside the grid
+  int me;         // own LDS cell
+  int ys;         // LDS distance of the y neighbours (z neighbours: 1)
+  int hcell;      // LDS cell this thread fills with a halo element, or the scratch cell
+  unsigned hoff;  // plane offset (voxels) of the element it loads for hcell, in range
+};
+
+// 2.5-D tile (tz, ty): 64 z voxels (one per lane) by TY rows (one per wave);
+// halo rows y0-1 / y0+TY and columns z0-1 / z0+64.  Halo elements outside
+// the grid go to the scratch cell: the cells they stand for feed held
+// voxels only.
+template <int TY>
+__device__ __forceinline__ LanePlace tile_place(int ny, int nz, int tz, int ty) {
   constexpr int W = TileSmem<TY>::W;
   constexpr int CELLS = TileSmem<TY>::CELLS;
   const int lane = threadIdx.x & 63;
@@ -119,30 +141,11 @@ __device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& 
   const int tid = threadIdx.x;
   const int z = tz * 64 + lane;
   const int y = ty * TY + wy;
-  const int x0 = tx * xc;
-  const bool inside = z < nz && y < ny;
-
-  TileCtx c;
-  c.nx = nx;
-  c.x1 = min(x0 + xc, nx);
-  c.xb = max(x0 - 1, 0);
-  c.psz = (unsigned)(ny * nz);
-  c.col = inside ? (unsigned)(y * nz + z) : 0u;
-  {
-    const size_t off = (size_t)c.xb * c.psz;
-    const size_t rest = (size_t)(nx - c.xb) * c.psz;
-    c.r.hi_in = make_rsrc(b.hi_in + off, rest * 4);
-    c.r.lo_in = make_rsrc(b.lo_in + off, rest * 4);
-    c.r.lab = make_rsrc(b.lab + off, rest);
-    c.r.src = make_rsrc(b.src + off, rest * 4);
-    c.r.om = make_rsrc(b.omega + off, rest * 4);
-    c.r.perf = make_rsrc(perf ? b.perf + off : b.src + off, rest * 4);
-    c.r.hi_out = make_rsrc(b.hi_out + off, rest * 4);
-    c.r.lo_out = make_rsrc(b.lo_out + off, rest * 4);
-  }
-
-  // Halo element owned by this thread (at most one): y rows y0-1 / y0+TY,
-  // z columns z0-1 / z0+64.  Threads without one write a scratch cell.
+  LanePlace p;
+  p.inside = z < nz && y < ny;
+  p.col = p.inside ? (unsigned)(y * nz + z) : 0u;
+  p.me = (wy + 1) * W + lane + 1;
+  p.ys = W;
   int hcell = CELLS, hy = -1, hz = -1;
   {
     const int y0 = ty * TY, z0 = tz * 64;
@@ -158,7 +161,72 @@ __device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& 
     }
     if (hy >= 0 && hy < ny && hz >= 0 && hz < nz) hcell = hrow * W + hcol;
   }
-  c.hoff = hcell < CELLS ? (unsigned)(hy * nz + hz) : c.col;
+  p.hcell = hcell;
+  p.hoff = hcell < CELLS ? (unsigned)(hy * nz + hz) : p.col;
+  return p;
+}
+
+// Flat segment t of a plane: voxels [t T, t T + T) in (y, z) order, one per
+// thread.  z neighbours are the adjacent cells (at a row's ends both the
+// voxel and the cell belong to the held outer layer), y neighbours nz cells
+// away; the nz voxels before and after the segment are the halo, loaded by
+// threads 0 .. 2 nz - 1 (nz <= T / 2).  Halo cells outside the plane are
+// filled from the thread's own column: finite values that feed held
+// voxels only.  Only a plane's last segment has idle lanes.
+template <int NW>
+__device__ __forceinline__ LanePlace flat_place(int ny, int nz, int t) {
+  constexpr int T = FlatSmem<NW>::T;
+  constexpr int CELLS = FlatSmem<NW>::CELLS;
+  const int i = threadIdx.x;
+  const int np = ny * nz;
+  const int f0 = t * T, f = f0 + i;
+  LanePlace p;
+  p.inside = f < np;
+  p.col = p.inside ? (unsigned)f : 0u;
+  p.me = nz + i;
+  p.ys = nz;
+  int h = -1;
+  p.hcell = CELLS;
+  if (i < nz) {
+    p.hcell = i; h = f0 - nz + i;
+  } else if (i < 2 * nz) {
+    p.hcell = nz + T + (i - nz); h = f0 + T + (i - nz);
+  }
+  p.hoff = (h >= 0 && h < np) ? (unsigned)h : p.col;
+  return p;
+}
+
+// March one work-group's placement over the x-chunk [tx*xc, tx*xc + xc) of
+// one grid.  ts / bs: the two LDS plane buffers (cells cells apart).  Tables
+// must be staged (a barrier inside the march orders them).  The
+// work-group's partial sums are written to partials[wg_slot * 3] if
+// partials is not null.
+template <int NT, int AUX>
+__device__ __forceinline__ void march(float2* ts, uint8_t* bs, int cells, float* red,
+                                      const float2* cf, const float4* cls,
+                                      const StepBuffers& b, const StepConst& K, bool perf,
+                                      int nx, int ny, int nz, int xc, int tx,
+                                      const LanePlace& lp, float* partials, int wg_slot) {
+  const int x0 = tx * xc;
+  TileCtx c;
+  c.nx = nx;
+  c.x1 = min(x0 + xc, nx);
+  c.xb = max(x0 - 1, 0);
+  c.psz = (unsigned)(ny * nz);
+  c.col = lp.col;
+  c.hoff = lp.hoff;
+  {
+    const size_t off = (size_t)c.xb * c.psz;
+    const size_t rest = (size_t)(nx - c.xb) * c.psz;
+    c.r.hi_in = make_rsrc(b.hi_in + off, rest * 4);
+    c.r.lo_in = make_rsrc(b.lo_in + off, rest * 4);
+    c.r.lab = make_rsrc(b.lab + off, rest);
+    c.r.src = make_rsrc(b.src + off, rest * 4);
+    c.r.om = make_rsrc(b.omega + off, rest * 4);
+    c.r.perf = make_rsrc(perf ? b.perf + off : b.src + off, rest * 4);
+    c.r.hi_out = make_rsrc(b.hi_out + off, rest * 4);
+    c.r.lo_out = make_rsrc(b.lo_out + off, rest * 4);
+  }
 
   // x-1 neighbour of the plane being computed (own column)
   float hm, lm;
@@ -174,9 +242,9 @@ __device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& 
   for (int k = 0; k < kAhead; ++k) load_plane(c, x0 + k, perf, q[k]);
 
   Partial acc{0.0f, 0.0f, 0u};
-  const int me = (wy + 1) * W + lane + 1;  // own LDS cell
-  const unsigned st4 = inside ? c.col * 4 : kOob;  // store offsets (out of range: dropped)
-  const unsigned st1 = inside ? c.col : kOob;
+  const int me = lp.me, ys = lp.ys, hcell = lp.hcell;
+  const unsigned st4 = lp.inside ? c.col * 4 : kOob;  // store offsets (out of range: dropped)
+  const unsigned st1 = lp.inside ? c.col : kOob;
 
   // One plane; S = ring slot of plane x (compile time), BUF = LDS buffer.
   auto plane_step = [&](auto S_, auto BUF_, int x) {
@@ -186,22 +254,24 @@ __device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& 
     constexpr int SL = (S + kAhead) % kSlots;  // slot receiving plane x+kAhead
     load_plane(c, x + kAhead, perf, q[SL]);
     const Plane& P = q[S];
-    sm.ts[BUF][me] = make_float2(P.h, P.l);
-    sm.bs[BUF][me] = (uint8_t)P.b;
-    sm.ts[BUF][hcell] = make_float2(P.hh, P.hl);
-    sm.bs[BUF][hcell] = (uint8_t)P.hb;
+    float2* t2 = ts + BUF * cells;
+    uint8_t* t1 = bs + BUF * cells;
+    t2[me] = make_float2(P.h, P.l);
+    t1[me] = (uint8_t)P.b;
+    t2[hcell] = make_float2(P.hh, P.hl);
+    t1[hcell] = (uint8_t)P.hb;
     __syncthreads();
-    const float2 ym = sm.ts[BUF][me - W], yp = sm.ts[BUF][me + W];
-    const float2 zm = sm.ts[BUF][me - 1], zp = sm.ts[BUF][me + 1];
-    const unsigned bym = sm.bs[BUF][me - W], byp = sm.bs[BUF][me + W];
-    const unsigned bzm = sm.bs[BUF][me - 1], bzp = sm.bs[BUF][me + 1];
+    const float2 ym = t2[me - ys], yp = t2[me + ys];
+    const float2 zm = t2[me - 1], zp = t2[me + 1];
+    const unsigned bym = t1[me - ys], byp = t1[me + ys];
+    const unsigned bzm = t1[me - 1], bzp = t1[me + 1];
     const Plane& N = q[SN];
     float nh, nl, om = P.om;
     unsigned nlab;
     const bool valid = x < c.x1;                        // uniform
     const unsigned lab = P.b | (valid ? 0u : kHeld);   // past the chunk: no contributions
     voxel_step(P.h, P.l, lab, hm, lm, bm, N.h, N.l, N.b, ym.x, ym.y, bym, yp.x, yp.y, byp,
-               zm.x, zm.y, bzm, zp.x, zp.y, bzp, P.s, P.pf, om, sm.cf, sm.cls, K, nh, nl, nlab,
+               zm.x, zm.y, bzm, zp.x, zp.y, bzp, P.s, P.pf, om, cf, cls, K, nh, nl, nlab,
                acc);
     {
       const int so = (min(x, c.x1 - 1) - c.xb) * (int)c.psz;  // uniform
@@ -228,7 +298,7 @@ __device__ __forceinline__ void tile_march(TileSmem<TY>& sm, const StepBuffers& 
     plane_step(I3{}, I1{}, x + 3);
   }
 
-  if (partials) write_partials(acc, &sm.red[0][0], TY, partials + (size_t)wg_slot * 3);
+  if (partials) write_partials(acc, red, NT, partials + (size_t)wg_slot * 3);
 }
 
 }  // namespace
@@ -243,19 +313,24 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled(StepBuffers b, StepConst
   const int tz = wg % tiles_z;
   const int ty = (wg / tiles_z) % tiles_y;
   const int tx = wg / (tiles_z * tiles_y);
-  tile_march<TY, AUX>(sm, b, K, PERF, nx, ny, nz, xc, tz, ty, tx, b.partials, wg);
+  const LanePlace lp = tile_place<TY>(ny, nz, tz, ty);
+  march<TY, AUX>(&sm.ts[0][0], &sm.bs[0][0], TileSmem<TY>::CELLS + 1, &sm.red[0][0], sm.cf,
+                 sm.cls, b, K, PERF, nx, ny, nz, xc, tx, lp, b.partials, wg);
 }
 
 // Batched step over the work list of all instances (items grouped by
 // instance).  LOOP: a persistent grid walks the list round-robin; otherwise
-// one work-group per item, in XCD-aware order.  Each item stages its
-// instance's tables before its march.  parity selects the ping-pong image.
-template <int TY, bool PERF, bool LOOP>
+// one work-group per item, in XCD-aware order.  FLAT: items are flat plane
+// segments of 64 TY voxels (item tz = segment), else 2.5-D tiles.  Each
+// item stages its instance's tables before its march.  parity selects the
+// ping-pong image.
+template <int TY, bool PERF, bool LOOP, bool FLAT>
 __global__ __launch_bounds__(64 * TY) void k_step_batch(const BatchInstance* inst,
                                                         const BatchItem* items, int first_item,
                                                         int n_items, int parity,
                                                         float* partials) {
-  __shared__ TileSmem<TY> sm;
+  using Smem = typename std::conditional<FLAT, FlatSmem<TY>, TileSmem<TY>>::type;
+  __shared__ Smem sm;
   // Work item and instance fields are the same for the whole work-group;
   // say so (readfirstlane), so descriptors and constants live in scalar
   // registers as in the single-grid kernel.
@@ -292,10 +367,16 @@ __global__ __launch_bounds__(64 * TY) void k_step_batch(const BatchInstance* ins
     K.cap = uf(I.K.cap);
     K.thr = uf(I.K.thr);
     stage_tables(sm.cf, sm.cls, b.tab, b.n_classes, 64 * TY);
+    const int ny = ui(I.ny), nz = ui(I.nz);
+    LanePlace lp;
+    if constexpr (FLAT)
+      lp = flat_place<TY>(ny, nz, ui(w.tz));
+    else
+      lp = tile_place<TY>(ny, nz, ui(w.tz), ui(w.ty));
     // groups of a batch are sized to stay in the last-level cache
-    tile_march<TY, kStoreBack>(sm, b, K, PERF, ui(I.nx), ui(I.ny), ui(I.nz), ui(I.xc),
-                               ui(w.tz), ui(w.ty),
-                   ui(w.tx), partials, it);
+    march<TY, kStoreBack>(&sm.ts[0][0], &sm.bs[0][0], Smem::CELLS + 1, &sm.red[0][0], sm.cf,
+                          sm.cls, b, K, PERF, ui(I.nx), ny, nz, ui(I.xc), ui(w.tx), lp,
+                          partials, it);
   };
   if (LOOP) {
     for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
@@ -307,17 +388,40 @@ __global__ __launch_bounds__(64 * TY) void k_step_batch(const BatchInstance* ins
   }
 }
 
-template <int TY, bool PERF>
+template <int TY, bool PERF, bool FLAT>
 static hipError_t launch_batch_ty(const BatchInstance* inst, const BatchItem* items,
                                   int first_item, int n_items, int n_wg, int parity,
                                   float* partials, hipStream_t st) {
   if (n_wg > 0)
-    hipLaunchKernelGGL((k_step_batch<TY, PERF, true>), dim3(n_wg), dim3(64 * TY), 0, st, inst,
-                       items, first_item, n_items, parity, partials);
-  else
-    hipLaunchKernelGGL((k_step_batch<TY, PERF, false>), dim3(n_items), dim3(64 * TY), 0, st,
+    hipLaunchKernelGGL((k_step_batch<TY, PERF, true, FLAT>), dim3(n_wg), dim3(64 * TY), 0, st,
                        inst, items, first_item, n_items, parity, partials);
+  else
+    hipLaunchKernelGGL((k_step_batch<TY, PERF, false, FLAT>), dim3(n_items), dim3(64 * TY), 0,
+                       st, inst, items, first_item, n_items, parity, partials);
   return hipGetLastError();
+}
+
+template <int TY, bool FLAT>
+static hipError_t launch_batch_ty(bool perf, const BatchInstance* inst, const BatchItem* items,
+                                  int first_item, int n_items, int n_wg, int parity,
+                                  float* partials, hipStream_t st) {
+  return perf ? launch_batch_ty<TY, true, FLAT>(inst, items, first_item, n_items, n_wg,
+                                                parity, partials, st)
+              : launch_batch_ty<TY, false, FLAT>(inst, items, first_item, n_items, n_wg,
+                                                 parity, partials, st);
+}
+
+int flat_max_nz(int ty) { return ty == 16 ? FlatSmem<16>::MAX_NZ : FlatSmem<8>::MAX_NZ; }
+
+TiledShape flat_shape(Grid3 g, int ty, int xc) {
+  TiledShape s;
+  s.ty = ty;
+  s.xc = xc;
+  s.tiles_z = (g.ny * g.nz + 64 * ty - 1) / (64 * ty);  // segments of a plane
+  s.tiles_y = 1;
+  s.chunks_x = (g.nx + xc - 1) / xc;
+  s.nwg = s.tiles_z * s.chunks_x;
+  return s;
 }
 
 TiledShape tiled_shape(Grid3 g, int ty, int xc) {
@@ -359,20 +463,22 @@ static hipError_t launch_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
   }
 }
 
-hipError_t launch_step_batch(int ty, bool perf, const BatchInstance* inst,
+hipError_t launch_step_batch(int ty, bool flat, bool perf, const BatchInstance* inst,
                              const BatchItem* items, int first_item, int n_items, int n_wg,
                              int parity, float* partials, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  if (ty == 4)
-    return perf ? launch_batch_ty<4, true>(inst, items, first_item, n_items, n_wg, parity,
-                                           partials, st)
-                : launch_batch_ty<4, false>(inst, items, first_item, n_items, n_wg, parity,
-                                            partials, st);
-  if (ty == 8)
-    return perf ? launch_batch_ty<8, true>(inst, items, first_item, n_items, n_wg, parity,
-                                           partials, st)
-                : launch_batch_ty<8, false>(inst, items, first_item, n_items, n_wg, parity,
-                                            partials, st);
+  if (!flat && ty == 4)
+    return launch_batch_ty<4, false>(perf, inst, items, first_item, n_items, n_wg, parity,
+                                     partials, st);
+  if (!flat && ty == 8)
+    return launch_batch_ty<8, false>(perf, inst, items, first_item, n_items, n_wg, parity,
+                                     partials, st);
+  if (flat && ty == 8)
+    return launch_batch_ty<8, true>(perf, inst, items, first_item, n_items, n_wg, parity,
+                                    partials, st);
+  if (flat && ty == 16)
+    return launch_batch_ty<16, true>(perf, inst, items, first_item, n_items, n_wg, parity,
+                                     partials, st);
   return hipErrorInvalidValue;
 }
 

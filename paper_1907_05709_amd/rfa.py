@@ -91,8 +91,8 @@ _SIGS = {
     "rfa_batch_create": [C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_double),
                          C.POINTER(C.c_void_p)],
     "rfa_batch_step": [C.c_void_p, C.c_int, C.c_void_p],
-    "rfa_batch_set_plan": [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_longlong],
-    "rfa_batch_get_plan": [C.c_void_p] + [C.POINTER(C.c_int)] * 5,
+    "rfa_batch_set_plan": [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_longlong],
+    "rfa_batch_get_plan": [C.c_void_p] + [C.POINTER(C.c_int)] * 6,
     "rfa_batch_last_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
     "rfa_batch_destroy": [C.c_void_p],
     "rfa_destroy_grid": [C.c_void_p],
@@ -321,17 +321,27 @@ def rfa_batch_step(b, n_steps: int, n_grids: int = 0, want_diag: bool = False):
     return [d.as_dict() for d in diags] if want_diag else None
 
 
+RFA_BATCH_TILES, RFA_BATCH_FLAT = 1, 2
+_LAYOUTS = {0: 0, "tiles": RFA_BATCH_TILES, "flat": RFA_BATCH_FLAT,
+            RFA_BATCH_TILES: RFA_BATCH_TILES, RFA_BATCH_FLAT: RFA_BATCH_FLAT}
+
+
 def rfa_batch_set_plan(b, tile_y: int = 0, tile_x: int = 0, workgroups: int = 0,
-                       group_voxels: int = -1):
-    _check(lib().rfa_batch_set_plan(b, int(tile_y), int(tile_x), int(workgroups),
-                                    int(group_voxels)))
+                       group_voxels: int = -1, layout=0):
+    """layout: 0 (keep), "tiles" or "flat" (or the RFA_BATCH_* values)."""
+    if layout not in _LAYOUTS:
+        raise RfaError(RFA_ERR_ARG, f"layout must be one of {sorted(map(str, _LAYOUTS))}")
+    _check(lib().rfa_batch_set_plan(b, _LAYOUTS[layout], int(tile_y), int(tile_x),
+                                    int(workgroups), int(group_voxels)))
 
 
 def rfa_batch_get_plan(b) -> dict:
-    v = [C.c_int() for _ in range(5)]
+    v = [C.c_int() for _ in range(6)]
     _check(lib().rfa_batch_get_plan(b, *[C.byref(x) for x in v]))
-    return dict(zip(("tile_y", "tile_x", "items", "workgroups", "groups"),
-                    [x.value for x in v]))
+    d = dict(zip(("layout", "tile_y", "tile_x", "items", "workgroups", "groups"),
+                 [x.value for x in v]))
+    d["layout"] = "flat" if d["layout"] == RFA_BATCH_FLAT else "tiles"
+    return d
 
 
 def rfa_batch_last_time(b):
@@ -557,8 +567,8 @@ class Batch:
         return rfa_batch_last_time(self.h)
 
     def set_plan(self, tile_y: int = 0, tile_x: int = 0, workgroups: int = 0,
-                 group_voxels: int = -1):
-        rfa_batch_set_plan(self.h, tile_y, tile_x, workgroups, group_voxels)
+                 group_voxels: int = -1, layout=0):
+        rfa_batch_set_plan(self.h, tile_y, tile_x, workgroups, group_voxels, layout)
         return self.plan()
 
     def plan(self) -> dict:

@@ -37,17 +37,20 @@ def state(g):
     return hi, lo, m, om
 
 
-@pytest.mark.parametrize("group_voxels", [-1, 120_000, 0])
-def test_batch_bitwise_equals_single_grids_and_replays(group_voxels):
+@pytest.mark.parametrize("group_voxels,layout", [(-1, "tiles"), (120_000, "tiles"), (0, "tiles"),
+                                                 (-1, "flat"), (120_000, "flat"), (0, "flat")])
+def test_batch_bitwise_equals_single_grids_and_replays(group_voxels, layout):
     """Default grouping, several small groups (each runs all its steps before
-    the next), and all grids in lockstep."""
+    the next), and all grids in lockstep; work items as 2.5-D tiles and as
+    flat plane segments."""
     from paper_1907_05709_amd import rfa
     cases = small_sweep()
     assert len({c.shape for c in cases}) > 2          # uneven grids
     singles = [grid_for(c) for c in cases]
     batched = [grid_for(c) for c in cases]
     b = rfa.Batch(batched, [c.dt for c in cases])
-    plan = b.set_plan(0, 0, 0, group_voxels)
+    plan = b.set_plan(0, 0, 0, group_voxels, layout)
+    assert plan["layout"] == layout
     if group_voxels == 120_000:
         assert plan["groups"] > 1
     elif group_voxels == 0:
@@ -68,8 +71,9 @@ def test_batch_bitwise_equals_single_grids_and_replays(group_voxels):
         g.close()
 
 
-@pytest.mark.parametrize("workgroups", [0, 7])
-def test_batch_mixed_perfusion_fields_and_persistent_plan(workgroups):
+@pytest.mark.parametrize("workgroups,layout", [(0, "tiles"), (7, "tiles"), (0, "flat"),
+                                               (7, "flat")])
+def test_batch_mixed_perfusion_fields_and_persistent_plan(workgroups, layout):
     """Grids with a perfusion multiplier field run in their own launch; the
     persistent schedule (few work-groups walking the item list) and the
     one-work-group-per-item schedule give the same bits as single grids."""
@@ -86,7 +90,7 @@ def test_batch_mixed_perfusion_fields_and_persistent_plan(workgroups):
             g2.set_perfusion(f)
     dts = [0.9 * min(c.dt, g.dt_max()) for c, g in zip(cases, singles)]
     b = rfa.Batch(batched, dts)
-    b.set_plan(0, 0, workgroups)
+    b.set_plan(0, 0, workgroups, -1, layout)
     plan = b.plan()
     if workgroups:
         assert plan["workgroups"] <= 2 * workgroups
@@ -126,14 +130,15 @@ def test_batch_resyncs_after_a_grid_is_stepped_alone():
         g.close()
 
 
-@pytest.mark.parametrize("group_voxels", [-1, 100_000])
-def test_batch_diagnostics_match_single_grids(group_voxels):
+@pytest.mark.parametrize("group_voxels,layout", [(-1, "tiles"), (100_000, "tiles"),
+                                                 (-1, "flat")])
+def test_batch_diagnostics_match_single_grids(group_voxels, layout):
     from paper_1907_05709_amd import rfa
     cases = small_sweep(n_inst=4, seed=4300)
     singles = [grid_for(c) for c in cases]
     batched = [grid_for(c) for c in cases]
     b = rfa.Batch(batched, [c.dt for c in cases])
-    b.set_plan(0, 0, 0, group_voxels)
+    b.set_plan(0, 0, 0, group_voxels, layout)
     d_b = b.step(70, diag=True)                       # crosses a reduction boundary
     for g, c, db in zip(singles, cases, d_b):
         ds = g.step(70, c.dt, diag=True)
@@ -178,11 +183,26 @@ def test_batch_rejects_unstable_dt_and_bad_args():
     assert e.value.status == rfa.RFA_ERR_ARG
     b = rfa.Batch(grids, [c.dt for c in cases])
     before = b.plan()
-    for bad in (dict(tile_y=6), dict(tile_x=-1), dict(workgroups=-2)):
+    assert (before["layout"], before["tile_y"]) == ("flat", 8)   # default for nz <= 256
+    for bad in (dict(tile_y=6), dict(tile_x=-1), dict(workgroups=-2), dict(layout=3),
+                dict(layout="flat", tile_y=4)):
         with pytest.raises(rfa.RfaError) as e:
             b.set_plan(**bad)
         assert e.value.status == rfa.RFA_ERR_ARG
     assert b.plan() == before
     b.close()
+    # flat segments of 8 waves cover grids up to nz = 256; 16 waves up to 512
+    deep = W.random_tissue_case(4501, shape=(6, 5, 300), n_classes=3, n_tines=1, n_steps=4)
+    gd = grid_for(deep)
+    b = rfa.Batch([grids[0], gd], [cases[0].dt, deep.dt])
+    before = b.plan()
+    assert (before["layout"], before["tile_y"]) == ("tiles", 4)
+    with pytest.raises(rfa.RfaError) as e:
+        b.set_plan(tile_y=8, layout="flat")
+    assert e.value.status == rfa.RFA_ERR_ARG
+    assert b.plan() == before
+    assert b.set_plan(tile_y=16, layout="flat")["layout"] == "flat"
+    b.close()
+    gd.close()
     for g in grids:
         g.close()
