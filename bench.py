@@ -39,18 +39,21 @@ HBM_PEAK_GBPS = 8000.0
 # reductions between blocks; 64 rather than 16 keeps the event records'
 # own cost (about 3 % of a 13 us launch) out of the measured throughput.
 TIME_PERIOD = 64
-KERNEL_SOURCES = ("paper_1907_05709_amd/csrc/rfa_tiled.hip",
-                  "paper_1907_05709_amd/csrc/rfa_wide.hip",
-                  "paper_1907_05709_amd/csrc/rfa_tiled.h",
-                  "paper_1907_05709_amd/csrc/rfa_tile_common.h",
-                  "paper_1907_05709_amd/csrc/rfa_device.h",
-                  "paper_1907_05709_amd/csrc/rfa_kernels.h")
+# Sources that define each step kernel's device code; a committed traffic
+# record applies while they hash as they did when its counters were taken.
+_CSRC = "paper_1907_05709_amd/csrc/"
+_SHARED = ("rfa_tile_common.h", "rfa_device.h", "rfa_kernels.h")
+KERNEL_SOURCES = {
+    "k_step_wide": ("rfa_wide.hip",) + _SHARED,
+    "k_step_tiled": ("rfa_tiled.hip", "rfa_tiled.h") + _SHARED,
+    "k_step_batch": ("rfa_tiled.hip", "rfa_tiled.h") + _SHARED,
+}
 
 
-def kernel_hash() -> str:
+def kernel_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, _CSRC + f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -85,15 +88,16 @@ def workload(config: int):
     return case, name
 
 
-def traffic_record(config: int, plan: dict):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if
-    they were taken on the current kernel sources and launch plan."""
+def traffic_record(config: int, plan: dict, kernel: str):
+    """Bytes per launch below L2 from committed rocprofv3 counter summaries,
+    if they were taken on the kernel's current sources and launch plan."""
     path = os.path.join(ROOT, "profiles", f"traffic_step_config{config}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_hash") != kernel_hash() or rec.get("plan") != plan:
+    if (kernel not in KERNEL_SOURCES or rec.get("kernel_hash") != kernel_hash(kernel)
+            or rec.get("plan") != plan):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -173,7 +177,7 @@ def main():
     avg_ms = kms / launches
     bytes_per_launch = BYTES_PER_VOXEL_STEP * case.n_voxels
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = traffic_record(args.config, plan)
+    traffic = traffic_record(args.config, plan, kernel_name(plan))
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -281,7 +285,7 @@ def bench_batch(args):
                    "batched_speedup_vs_plain": round(value / seq_value, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic_record(4, plan), "kernel": "k_step_batch",
+                     "traffic": traffic_record(4, plan, "k_step_batch"), "kernel": "k_step_batch",
                      "avg_launch_us": round(avg_launch_ms * 1e3, 3),
                      "bytes_per_launch": round(bytes_per_launch),
                      "note": "groups of grids sized to the 256 MB last-level cache run "
