@@ -20,10 +20,10 @@ OMEGA_RTOL = 2e-3
 
 
 def gpu_run(case, n_steps=None, depth=0, device=False, diag=True, dt=None, kernel=0,
-            tile_y=0, tile_x=0):
+            tile_y=0, tile_x=0, z_vec=0):
     from paper_1907_05709_amd import rfa
     g = rfa.Grid(case.shape, case.spacing, device=device, depth=depth, kernel=kernel,
-                 tile_y=tile_y, tile_x=tile_x,
+                 tile_y=tile_y, tile_x=tile_x, z_vec=z_vec,
                  t_death=case.t_death, A=case.arrhenius_a, Ea=case.arrhenius_ea,
                  R=case.gas_r, omega_cap=case.omega_cap)
     g.load_case(case)
