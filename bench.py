@@ -297,12 +297,14 @@ def bench_batch(args):
 
 def bench_adjoint(args):
     """Differentiation workload: 128^3 at 0.5 mm, 9-tine umbrella (60 W
-    shared by length), 600 steps of 0.02 s, checkpoint every 50 steps,
-    perfusion corrected by a 16^3 B-spline lattice (all zero).  One bench
-    step = reset, checkpointed forward, coverage loss and its gradient with
-    respect to the damage integral (torch, on the GPU), adjoint to the 9 tine
-    powers and the 4096 lattice values.  value = simulated voxel-steps per
-    second of forward + adjoint."""
+    shared by length), 600 steps of 0.02 s, perfusion corrected by a 16^3
+    B-spline lattice (all zero).  One bench step = reset, forward keeping the
+    temperature of every step in HBM (5 GB), coverage loss and its gradient
+    with respect to the damage integral (torch, on the GPU), adjoint to the 9
+    tine powers and the 4096 lattice values.  value = simulated voxel-steps
+    per second of forward + adjoint.  The checkpointed schedule (state every
+    50 steps, each segment recomputed in the adjoint; same gradients, bitwise)
+    is timed beside it."""
     import numpy as np
     import torch
     from paper_1907_05709_amd import rfa
@@ -311,7 +313,7 @@ def bench_adjoint(args):
 
     n_steps = args.time_steps if args.time_steps > 0 else 600
     case = W.case_differentiation(n_steps=n_steps)
-    m, every = 16, 50
+    m, ckpt = 16, 50
     g = rfa.Grid(case.shape, case.spacing, device=True, time_kernels=TIME_PERIOD)
     g.load_case(case)
     g.set_perfusion_bspline(np.zeros((m, m, m), np.float32))
@@ -319,7 +321,7 @@ def bench_adjoint(args):
     labels = torch.from_numpy(case.labels).cuda()
     vox = float(np.prod(case.spacing))
 
-    def one_step():
+    def one_step(every=0):
         g.reset_state()
         g.forward_checkpointed(n_steps, case.dt, every)
         _, om, _ = g.damage()
@@ -339,6 +341,14 @@ def bench_adjoint(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kms, launches, _ = g.kernel_stats()
+    # the checkpointed schedule, for comparison (not part of value)
+    _, dP_ck = one_step(ckpt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step(ckpt)
+    torch.cuda.synchronize()
+    ck_value = case.n_voxels * n_steps * args.steps / (time.perf_counter() - t1) / 1e9
     g.close()
     value = case.n_voxels * n_steps * args.steps / wall / 1e9
     avg_ms = kms / max(launches, 1)
@@ -358,8 +368,11 @@ def bench_adjoint(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"differentiation: 9-tine umbrella 128^3 @0.5mm, {n_steps} x "
-                               f"{case.dt} s, checkpoint every {every}, 16^3 B-spline perfusion "
-                               f"lattice; value counts forward + adjoint per simulated step",
+                               f"{case.dt} s, 16^3 B-spline perfusion lattice; value counts "
+                               f"forward + adjoint per simulated step",
+                   "trajectory": "every step's temperature kept in HBM, no recomputation",
+                   "checkpointed_every_%d_GVox_s" % ckpt: round(ck_value, 3),
+                   "checkpointed_gradients_equal": bool(np.array_equal(dP, dP_ck)),
                    "loss": loss, "dL_dP": [float(x) for x in dP]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),

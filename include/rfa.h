@@ -225,11 +225,13 @@ rfa_status rfa_copy_bandwidth(size_t bytes, int reps, double* gbps);
 /* ---- Differentiation -------------------------------------------------------
  * The damage integral after N steps, Omega^N (Eq. (eq-tissState) summed by
  * the stepper), is a differentiable function of the tine powers and of the
- * perfusion field.  rfa_forward_checkpointed runs the forward keeping the
- * temperature state every ckpt_every steps; rfa_adjoint then runs the exact
- * discrete adjoint of those steps backwards (recomputing each segment from
- * its checkpoint, bitwise as in the forward) for a loss whose gradient with
- * respect to Omega^N is given.  The adjoint differentiates the damage rate
+ * perfusion field.  rfa_forward_checkpointed runs the forward keeping either
+ * the temperature of every step (ckpt_every = 0; (N + 1) * 4 bytes per voxel
+ * of device memory, 5 GB for 128^3 x 600 steps) or the state every
+ * ckpt_every steps; rfa_adjoint then runs the exact discrete adjoint of
+ * those steps backwards (with checkpoints, recomputing each segment from its
+ * checkpoint, bitwise as in the forward, so both schedules give the same
+ * gradients) for a loss whose gradient with respect to Omega^N is given.  The adjoint differentiates the damage rate
  * where its exponent cap is inactive and voxels whose Omega^N reached the
  * cap not at all; latches are not differentiable and do not enter. */
 
@@ -247,8 +249,11 @@ rfa_status rfa_reset_state(rfa_grid g);
 /* New tine powers (W, [n_tines]) for the current needle geometry. */
 rfa_status rfa_set_tine_powers(rfa_grid g, const double* power);
 
-/* n_steps forward steps (as rfa_step) keeping the state at steps
- * 0, ckpt_every, 2 ckpt_every, ... for rfa_adjoint. */
+/* n_steps forward steps (as rfa_step) keeping, for rfa_adjoint, the
+ * temperature (hi word) of every step when ckpt_every = 0 (one step per
+ * launch, written straight into the kept trajectory; RFA_ERR_OOM if it does
+ * not fit: use checkpoints), else the state at steps 0, ckpt_every,
+ * 2 ckpt_every, ... */
 rfa_status rfa_forward_checkpointed(rfa_grid g, int n_steps, double dt, int ckpt_every);
 
 /* Adjoint of the last rfa_forward_checkpointed (the grid must not have

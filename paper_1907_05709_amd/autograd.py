@@ -3,10 +3,12 @@ B-spline perfusion-correction lattice.
 
 RfaFunction.apply(powers, ctrl, grid, n_steps, dt, ckpt_every) resets the
 grid, sets the powers (W, one per tine) and the perfusion multiplier
-f = exp(B ctrl), runs the checkpointed forward and returns Omega^N (the
-Arrhenius damage integral per voxel) as a tensor on the grid's device.
-backward() runs the library's discrete adjoint (recomputing each segment
-from its checkpoint) and returns dL/dpowers and dL/dctrl.  All computation
+f = exp(B ctrl), runs the forward (ckpt_every = 0: keeping every step's
+temperature in device memory; k > 0: a checkpoint every k steps) and returns
+Omega^N (the Arrhenius damage integral per voxel) as a tensor on the grid's
+device.  backward() runs the library's discrete adjoint (from the kept
+trajectory, or recomputing each segment from its checkpoint) and returns
+dL/dpowers and dL/dctrl.  All computation
 is in librfa.so; this module only moves arguments.
 """
 from __future__ import annotations

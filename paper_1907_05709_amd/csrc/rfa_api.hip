@@ -414,9 +414,19 @@ rfa_status ensure_events(rfa_grid g, int count);
 // Advance the grid's current state n_steps with its launch plan (step
 // partials into g->dacc when diag), timing launch blocks with HIP events
 // when the grid was created with time_kernels.  Updates the step count.
-rfa_status timed_steps(rfa_grid g, const StepConst& K, int n_steps, bool diag) {
+// With traj: one step per launch, the hi image of step *traj_t read from
+// traj[*traj_t] and written to traj[*traj_t + 1] (the grid's hi images are
+// not touched).
+rfa_status timed_steps(rfa_grid g, const StepConst& K, int n_steps, bool diag,
+                       float* traj = nullptr, int* traj_t = nullptr) {
   StepState ss{g->hi, g->lo, &g->cur, g->lab, g->src, g->om, g->perf, g->tab_dev,
                g->n_classes};
+  const StepPlan plan = traj ? plan_one(g->plan) : g->plan;
+  if (traj) {
+    ss.traj = traj;
+    ss.traj_t = traj_t;
+    ss.traj_n = g->g.n();
+  }
   rfa_status s = RFA_OK;
   for (int done = 0; done < n_steps;) {
     const int batch = std::min(n_steps - done, kTimedBatch);
@@ -426,7 +436,7 @@ rfa_status timed_steps(rfa_grid g, const StepConst& K, int n_steps, bool diag) {
       ev = g->events.data();
     }
     int timed = 0, launches = 0;
-    s = run_steps(g->g, g->plan, ss, K, batch, diag ? g->partials : nullptr, kPartialSlots,
+    s = run_steps(g->g, plan, ss, K, batch, diag ? g->partials : nullptr, kPartialSlots,
                   g->dacc, ev, g->opt.time_kernels, &timed, &launches, g->st);
     if (s != RFA_OK)
       return fail(s, "step launch failed: %s", hipGetErrorString(hipGetLastError()));
@@ -438,7 +448,7 @@ rfa_status timed_steps(rfa_grid g, const StepConst& K, int n_steps, bool diag) {
         g->kernel_ms += ms;
       }
       g->kernel_launches += launches;
-      g->kernel_voxel_steps += (long long)launches * g->plan.depth * (long long)g->g.n();
+      g->kernel_voxel_steps += (long long)launches * plan.depth * (long long)g->g.n();
     }
     done += batch;
     g->steps += batch;
@@ -1216,13 +1226,41 @@ rfa_status rfa_set_tine_powers(rfa_grid g, const double* power) {
 rfa_status rfa_forward_checkpointed(rfa_grid g, int n_steps, double dt, int ckpt_every) {
   if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
   if (!g->has_tissue) return fail(RFA_ERR_STATE, "set_tissue before forward");
-  if (n_steps < 1 || ckpt_every < 1) return fail(RFA_ERR_ARG, "n_steps, ckpt_every >= 1");
+  if (n_steps < 1 || ckpt_every < 0) return fail(RFA_ERR_ARG, "n_steps >= 1, ckpt_every >= 0");
   if (!finite_pos(dt)) return fail(RFA_ERR_ARG, "dt must be finite and positive");
   if (dt > g->dt_max)
     return fail(RFA_ERR_UNSTABLE, "dt %.6g s exceeds the stability bound %.6g s", dt, g->dt_max);
   rfa_status s = prepare_dt(g, dt);
   if (s != RFA_OK) return s;
   const size_t n = g->g.n();
+  if (ckpt_every == 0) {
+    // the whole hi trajectory, written by the steps themselves
+    const size_t need = (size_t)(n_steps + 1) * n;
+    if (g->traj_floats < need) {
+      if (g->traj) (void)hipFree(g->traj);
+      g->traj = nullptr;
+      g->traj_floats = 0;
+      if ((s = dmalloc(&g->traj, need)) != RFA_OK) return s;
+      g->traj_floats = need;
+    }
+    g->adj_ready = false;
+    const StepConst K = step_const(g, dt);
+    HIP_TRY(hipMemcpyAsync(g->traj, g->hi[g->cur], n * sizeof(float), hipMemcpyDeviceToDevice,
+                           g->st));
+    int t = 0;
+    if ((s = timed_steps(g, K, n_steps, false, g->traj, &t)) != RFA_OK) return s;
+    HIP_TRY(hipMemcpyAsync(g->hi[g->cur], g->traj + (size_t)n_steps * n, n * sizeof(float),
+                           hipMemcpyDeviceToDevice, g->st));
+    g->energy_valid = false;
+    ++g->version;
+    g->adj_ready = true;
+    g->adj_version = g->version;
+    g->adj_steps = n_steps;
+    g->adj_every = 0;
+    g->adj_nckpt = 0;
+    g->adj_dt = dt;
+    return RFA_OK;
+  }
   const int every = std::min(ckpt_every, n_steps);
   const int nck = (n_steps + every - 1) / every;
   const size_t need = (size_t)nck * 2 * n;
@@ -1262,10 +1300,10 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
   if (dL_dctrl && !g->bs_m) return fail(RFA_ERR_STATE, "no B-spline perfusion field");
   if (dL_dP && !g->has_needle) return fail(RFA_ERR_STATE, "no needle");
   const size_t n = g->g.n();
-  const int every = g->adj_every;
+  const int every = g->adj_every;  // 0: the forward kept the whole trajectory
   rfa_status s;
   const size_t tneed = (size_t)(every + 1) * n;
-  if (g->traj_floats < tneed) {
+  if (every > 0 && g->traj_floats < tneed) {
     if (g->traj) (void)hipFree(g->traj);
     g->traj = nullptr;
     g->traj_floats = 0;
@@ -1296,6 +1334,25 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
   }
   const bool tiled_adj = g->plan.kind != kStepNaive && adjoint_tiled_fits(g->g, adj_xc);
   int lc = 0;
+  // adjoint step from theta^t = traj[t]
+  auto adjoint_step = [&](const float* theta) {
+    AdjointBuffers a;
+    a.lam_in = lam[lc];
+    a.lam_out = lam[1 - lc];
+    a.theta = theta;
+    a.lab = g->lab;
+    a.perf = g->perf;
+    a.w = wv;
+    a.tab = g->tab_dev;
+    a.sacc = sacc;
+    a.facc = facc;
+    lc = 1 - lc;
+    return tiled_adj ? launch_adjoint_tiled(g->g, 4, adj_xc, a, K, g->st)
+                     : launch_adjoint_step(g->g, a, K, g->st);
+  };
+  if (every == 0)  // the forward kept every theta^t: no recomputation
+    for (int t = g->adj_steps - 1; t >= 0; --t)
+      HIP_TRY(adjoint_step(g->traj + (size_t)t * n));
   for (int seg = g->adj_nckpt - 1; seg >= 0; --seg) {
     const int k = std::min(every, g->adj_steps - seg * every);
     const float* c = g->ckpt + (size_t)seg * 2 * n;
@@ -1316,23 +1373,7 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
       b.n_classes = g->n_classes;
       HIP_TRY(launch_plan(g->g, plan_one(g->plan), b, K, g->st));
     }
-    for (int t = k - 1; t >= 0; --t) {
-      AdjointBuffers a;
-      a.lam_in = lam[lc];
-      a.lam_out = lam[1 - lc];
-      a.theta = g->traj + (size_t)t * n;
-      a.lab = g->lab;
-      a.perf = g->perf;
-      a.w = wv;
-      a.tab = g->tab_dev;
-      a.sacc = sacc;
-      a.facc = facc;
-      if (tiled_adj)
-        HIP_TRY(launch_adjoint_tiled(g->g, 4, adj_xc, a, K, g->st));
-      else
-        HIP_TRY(launch_adjoint_step(g->g, a, K, g->st));
-      lc = 1 - lc;
-    }
+    for (int t = k - 1; t >= 0; --t) HIP_TRY(adjoint_step(g->traj + (size_t)t * n));
   }
   if (dL_dP) {
     const int nt = (int)g->power.size();

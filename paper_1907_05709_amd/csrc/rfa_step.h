@@ -52,6 +52,12 @@ struct StepState {
   const float* perf;
   const Tables* tab;
   int n_classes;
+  // Trajectory mode (traj not null, one-step plans only): the hi image of
+  // step *traj_t is read from traj[*traj_t] and written to traj[*traj_t + 1]
+  // (images of traj_n voxels); lo keeps ping-ponging in lo[2].
+  float* traj = nullptr;
+  int* traj_t = nullptr;
+  size_t traj_n = 0;
 };
 
 // One launch of the plan (plan.depth steps) from b's input to its output image.

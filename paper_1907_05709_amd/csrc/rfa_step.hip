@@ -195,12 +195,18 @@ hipError_t launch_plan(Grid3 g, const StepPlan& plan, const StepBuffers& b, cons
 rfa_status run_steps(Grid3 g, const StepPlan& plan, StepState& s, const StepConst& K,
                      int n_steps, float* partials, int slots, double* dacc, hipEvent_t* events,
                      int period, int* n_timed, int* n_launches, hipStream_t st) {
+  if (s.traj && plan.depth != 1) return RFA_ERR_ARG;
   auto buffers = [&]() {
     StepBuffers b;
     b.hi_in = s.hi[*s.cur];
     b.lo_in = s.lo[*s.cur];
     b.hi_out = s.hi[1 - *s.cur];
     b.lo_out = s.lo[1 - *s.cur];
+    if (s.traj) {
+      float* h = s.traj + (size_t)*s.traj_t * s.traj_n;
+      b.hi_in = h;
+      b.hi_out = h + s.traj_n;
+    }
     b.lab = s.lab;
     b.src = s.src;
     b.omega = s.om;
@@ -223,6 +229,7 @@ rfa_status run_steps(Grid3 g, const StepPlan& plan, StepState& s, const StepCons
     const bool close = events && ((n % period) == period - 1 || n == n_main - 1);
     if (open && hipEventRecord(events[2 * timed], st) != hipSuccess) return RFA_ERR_HIP;
     if (launch_plan(g, plan, b, K, st) != hipSuccess) return RFA_ERR_HIP;
+    if (s.traj) ++*s.traj_t;
     if (close) {
       if (hipEventRecord(events[2 * timed + 1], st) != hipSuccess) return RFA_ERR_HIP;
       ++timed;

@@ -146,7 +146,7 @@ def test_checkpoint_spacing_does_not_change_gradients(setup):
     P = case.needle.power.copy()
     g.set_tine_powers(P)
     out = []
-    for every in (EVERY, N_STEPS, 1):
+    for every in (EVERY, N_STEPS, 1, 0):   # 0: the whole trajectory kept, no recomputation
         g.reset_state()
         g.forward_checkpointed(N_STEPS, DT, every)
         _, om, _ = g.damage()
@@ -155,6 +155,8 @@ def test_checkpoint_spacing_does_not_change_gradients(setup):
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
     for a, b in zip(out[0], out[2]):
+        assert np.array_equal(a, b)
+    for a, b in zip(out[0], out[3]):
         assert np.array_equal(a, b)
     g.close()
 
