@@ -241,6 +241,8 @@ def bench_batch(args):
     seq_value = total_vox * n_steps / seq_wall / 1e9
 
     b = rfa.Batch(grids, [c.dt for c in cases])
+    if args.tune:
+        b.tune(reps=20)
     for _ in range(args.warmup):
         b.step(n_steps)
     torch.cuda.synchronize()

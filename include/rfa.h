@@ -319,6 +319,16 @@ rfa_status rfa_batch_set_plan(rfa_batch b, int layout, int tile_y, int tile_x, i
 rfa_status rfa_batch_get_plan(rfa_batch b, int* layout, int* tile_y, int* tile_x, int* items,
                               int* workgroups, int* groups);
 
+/* Pick the batch's launch shape by timing: work-item layouts, tile rows and
+ * x planes per item at the default grouping, then grouping budgets for the
+ * fastest shape (0 included: lockstep), each over reps steps of all grids
+ * (one untimed replay first); keeps the fastest.  The grids' states are
+ * snapshotted in device memory (13 bytes per voxel) and restored, so the
+ * batch and its grids are left exactly as they were apart from the plan.
+ * Batch work items take one step per launch; see rfa_tune for the
+ * single-grid temporal blocking depth. */
+rfa_status rfa_batch_tune(rfa_batch b, int reps);
+
 /* Device time of the last rfa_batch_step's graph, milliseconds (HIP events
  * on the batch's stream), and voxel-steps it advanced. */
 rfa_status rfa_batch_last_time(rfa_batch b, double* ms, long long* voxel_steps);

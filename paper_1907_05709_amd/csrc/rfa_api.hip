@@ -109,7 +109,7 @@ struct rfa_grid_s {
   double adj_dt = 0.0;
   float* ckpt = nullptr;           // [nckpt][2][N] hi, lo at segment starts
   size_t ckpt_floats = 0;
-  float* traj = nullptr;           // [every + 1][N] recomputed hi
+  float* traj = nullptr;           // hi images: the kept trajectory [N + 1] or a segment [every + 1]
   size_t traj_floats = 0;
   float* adj_work = nullptr;       // lo ping-pong (2N), lambda (2N), sacc, facc, w, omega scratch
   uint8_t* lab_scratch = nullptr;
@@ -1789,6 +1789,132 @@ rfa_status rfa_batch_get_plan(rfa_batch b, int* layout, int* tile_y, int* tile_x
   }
   if (groups) *groups = (int)b->groups.size();
   return RFA_OK;
+}
+
+rfa_status rfa_batch_tune(rfa_batch b, int reps) {
+  if (!b) return fail(RFA_ERR_ARG, "batch is NULL");
+  if (reps < 1) return fail(RFA_ERR_ARG, "reps must be >= 1");
+  const int n = (int)b->grids.size();
+  rfa_status s;
+  if (!batch_in_sync(b) && (s = batch_build(b)) != RFA_OK) return s;
+  // snapshot of what a step reads and writes: the current images, damage
+  // and latch bytes (the other images are scratch to the batch)
+  std::vector<void*> snap(4 * (size_t)n, nullptr);
+  auto release = [&]() {
+    for (void* p : snap)
+      if (p) (void)hipFree(p);
+  };
+  auto copy_state = [&](bool save) -> hipError_t {
+    for (int i = 0; i < n; ++i) {
+      rfa_grid g = b->grids[i];
+      const size_t nv = g->g.n();
+      void* live[4] = {g->hi[g->cur], g->lo[g->cur], g->om, g->lab};
+      const size_t bytes[4] = {nv * 4, nv * 4, nv * 4, nv};
+      for (int k = 0; k < 4; ++k) {
+        void* dst = save ? snap[4 * i + k] : live[k];
+        const void* src = save ? live[k] : snap[4 * i + k];
+        const hipError_t e = hipMemcpyAsync(dst, src, bytes[k], hipMemcpyDeviceToDevice, b->st);
+        if (e != hipSuccess) return e;
+      }
+    }
+    return hipStreamSynchronize(b->st);
+  };
+  for (int i = 0; i < n; ++i) {
+    HIP_TRY(hipStreamSynchronize(b->grids[i]->st));
+    const size_t nv = b->grids[i]->g.n();
+    for (int k = 0; k < 4; ++k) {
+      uint8_t* p = nullptr;
+      if ((s = dmalloc(&p, k < 3 ? 4 * nv : nv)) != RFA_OK) {
+        release();
+        return s;
+      }
+      snap[4 * i + k] = p;
+    }
+  }
+  hipError_t e = copy_state(true);
+  if (e != hipSuccess) {
+    release();
+    return fail(RFA_ERR_HIP, "tune snapshot: %s", hipGetErrorString(e));
+  }
+  struct Cand {
+    bool flat;
+    int ty, xc;
+    long long group;
+  };
+  bool flat_ok = true;
+  for (rfa_grid g : b->grids) flat_ok = flat_ok && g->g.nz <= flat_max_nz(8);
+  const long long g0 = kBatchGroupVoxels;
+  std::vector<Cand> shapes = {{false, 4, 8, g0}, {false, 8, 8, g0}, {false, 4, 16, g0}};
+  if (flat_ok) shapes.insert(shapes.begin(), {{true, 8, 8, g0}, {true, 8, 4, g0}, {true, 8, 16, g0}});
+  const Cand keep{b->flat, b->ty, b->xc, b->group_budget};
+  const int keep_wg = b->req_wg;
+  // time reps steps of one candidate (after one untimed replay), then put
+  // the state back; ms < 0 on failure
+  auto time_cand = [&](const Cand& c, double* ms) -> rfa_status {
+    b->flat = c.flat;
+    b->ty = c.ty;
+    b->xc = c.xc;
+    b->group_budget = c.group;
+    b->req_wg = 0;
+    rfa_status st = batch_build(b);
+    if (st != RFA_OK) return st;
+    hipGraphExec_t exec = nullptr;
+    if ((st = batch_graph(b, reps, false, &exec)) != RFA_OK) return st;
+    HIP_TRY(hipGraphLaunch(exec, b->st));
+    HIP_TRY(hipEventRecord(b->ev0, b->st));
+    HIP_TRY(hipGraphLaunch(exec, b->st));
+    HIP_TRY(hipEventRecord(b->ev1, b->st));
+    HIP_TRY(hipEventSynchronize(b->ev1));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, b->ev0, b->ev1));
+    *ms = t;
+    const hipError_t er = copy_state(false);
+    if (er != hipSuccess) return fail(RFA_ERR_HIP, "tune restore: %s", hipGetErrorString(er));
+    return RFA_OK;
+  };
+  Cand best = keep;
+  double best_ms = -1.0;
+  auto consider = [&](const Cand& c) -> rfa_status {
+    double ms = 0.0;
+    const rfa_status st = time_cand(c, &ms);
+    if (st != RFA_OK) return st;
+    if (best_ms < 0.0 || ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+    return RFA_OK;
+  };
+  // tile shapes at the default group budget, then group budgets for the best shape
+  for (const Cand& c : shapes)
+    if ((s = consider(c)) != RFA_OK) break;
+  if (s == RFA_OK) {
+    const Cand shape = best;
+    for (long long gv : {4ll << 20, 6ll << 20, 10ll << 20, 0ll}) {
+      Cand c = shape;
+      c.group = gv;
+      if ((s = consider(c)) != RFA_OK) break;
+    }
+  }
+  if (s != RFA_OK) {  // leave the batch as it was
+    std::string err = g_last_error;
+    (void)copy_state(false);
+    release();
+    b->flat = keep.flat;
+    b->ty = keep.ty;
+    b->xc = keep.xc;
+    b->group_budget = keep.group;
+    b->req_wg = keep_wg;
+    (void)batch_build(b);
+    g_last_error = err;
+    return s;
+  }
+  release();
+  b->flat = best.flat;
+  b->ty = best.ty;
+  b->xc = best.xc;
+  b->group_budget = best.group;
+  b->req_wg = 0;
+  return batch_build(b);
 }
 
 rfa_status rfa_batch_last_time(rfa_batch b, double* ms, long long* voxel_steps) {

@@ -93,6 +93,7 @@ _SIGS = {
     "rfa_batch_step": [C.c_void_p, C.c_int, C.c_void_p],
     "rfa_batch_set_plan": [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_longlong],
     "rfa_batch_get_plan": [C.c_void_p] + [C.POINTER(C.c_int)] * 6,
+    "rfa_batch_tune": [C.c_void_p, C.c_int],
     "rfa_batch_last_time": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
     "rfa_batch_destroy": [C.c_void_p],
     "rfa_destroy_grid": [C.c_void_p],
@@ -344,6 +345,10 @@ def rfa_batch_get_plan(b) -> dict:
     return d
 
 
+def rfa_batch_tune(b, reps: int = 20):
+    _check(lib().rfa_batch_tune(b, int(reps)))
+
+
 def rfa_batch_last_time(b):
     ms, vs = C.c_double(), C.c_longlong()
     _check(lib().rfa_batch_last_time(b, C.byref(ms), C.byref(vs)))
@@ -573,6 +578,11 @@ class Batch:
 
     def plan(self) -> dict:
         return rfa_batch_get_plan(self.h)
+
+    def tune(self, reps: int = 20) -> dict:
+        """Time candidate launch shapes and keep the fastest (grids unchanged)."""
+        rfa_batch_tune(self.h, reps)
+        return self.plan()
 
     def close(self):
         if getattr(self, "h", None):

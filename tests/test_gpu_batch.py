@@ -108,6 +108,31 @@ def test_batch_mixed_perfusion_fields_and_persistent_plan(workgroups, layout):
         g.close()
 
 
+def test_batch_tune_leaves_states_unchanged():
+    """The tuner times candidate plans on the live grids and restores them:
+    stepping on after tuning must match grids that were never tuned."""
+    from paper_1907_05709_amd import rfa
+    cases = small_sweep(n_inst=4, seed=4650)
+    singles = [grid_for(c) for c in cases]
+    batched = [grid_for(c) for c in cases]
+    b = rfa.Batch(batched, [c.dt for c in cases])
+    b.step(5)
+    for g, c in zip(singles, cases):
+        g.step(5, c.dt, diag=False)
+    plan = b.tune(reps=3)
+    assert plan["layout"] in ("flat", "tiles") and plan["groups"] >= 1
+    assert [g.step_count() for g in batched] == [5] * len(cases)
+    b.step(7)
+    for g, c in zip(singles, cases):
+        g.step(7, c.dt, diag=False)
+    for g1, g2 in zip(singles, batched):
+        for a1, a2 in zip(state(g1), state(g2)):
+            assert np.array_equal(a1, a2)
+    b.close()
+    for g in singles + batched:
+        g.close()
+
+
 def test_batch_resyncs_after_a_grid_is_stepped_alone():
     from paper_1907_05709_amd import rfa
     cases = small_sweep(n_inst=3, seed=4200)
