@@ -58,3 +58,32 @@ def coverage_loss(omega, labels, voxel_m3: float, tumour: int = 2, liver: int = 
     u = (1.0 - d[tum]).mean() if bool(tum.any()) else d.sum() * 0.0
     dv = d[liv].sum() * (voxel_m3 * 1e6)
     return u + healthy_weight * dv
+
+
+def optimise_plan(grid, labels, voxel_m3: float, powers, ctrl, n_steps: int, dt: float,
+                  iters: int = 10, lr_power: float = 1.0, lr_ctrl: float = 0.1,
+                  total_power=None, ckpt_every: int = 0):
+    """Projected Adam on the per-tine powers (W) and the B-spline perfusion
+    lattice for coverage_loss: after each update the powers are clipped at
+    0 and, with total_power, scaled back to that total; the lattice is
+    clipped to the library's |ctrl| <= 30.  Every iteration is one forward
+    and one adjoint in librfa.so (grid: a device grid with its tissue and
+    needle set).  Returns the final powers and lattice and the loss of every
+    iteration (evaluated before that iteration's update)."""
+    p = torch.as_tensor(np.asarray(powers), dtype=torch.float64).clone().requires_grad_(True)
+    c = torch.as_tensor(np.asarray(ctrl), dtype=torch.float32).clone().requires_grad_(True)
+    opt = torch.optim.Adam([{"params": [p], "lr": lr_power}, {"params": [c], "lr": lr_ctrl}])
+    losses = []
+    for _ in range(int(iters)):
+        opt.zero_grad()
+        omega = RfaFunction.apply(p, c, grid, n_steps, dt, ckpt_every)
+        loss = coverage_loss(omega, labels, voxel_m3)
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            p.clamp_(min=0.0)
+            if total_power is not None and float(p.sum()) > 0.0:
+                p.mul_(float(total_power) / p.sum())
+            c.clamp_(-30.0, 30.0)
+        losses.append(float(loss))
+    return p.detach(), c.detach(), losses

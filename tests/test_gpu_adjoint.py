@@ -189,3 +189,27 @@ def test_autograd_function_and_state_checks(setup):
     torch.cuda.synchronize()
     g.close()
     h.close()
+
+
+def test_projected_adam_plan_optimisation_lowers_the_loss(setup):
+    """The downstream use of the gradients: a few projected Adam steps on the
+    tine powers (fixed total power) and the perfusion lattice lower the
+    coverage loss, every iterate stays feasible."""
+    import torch
+    from paper_1907_05709_amd import rfa
+    from paper_1907_05709_amd.autograd import optimise_plan
+    case, ctrl = setup
+    g = rfa.Grid(case.shape, case.spacing, device=True)
+    g.load_case(case)
+    labels = torch.from_numpy(case.labels).cuda()
+    vox = float(np.prod(case.spacing))
+    P0 = case.needle.power.copy()
+    total = float(P0.sum())
+    P, c, losses = optimise_plan(g, labels, vox, P0, ctrl, N_STEPS, DT, iters=6,
+                                 lr_power=0.1 * total / len(P0), lr_ctrl=0.05,
+                                 total_power=total)
+    print("coverage loss per iteration:", [f"{x:.5f}" for x in losses])
+    assert min(losses[1:]) < losses[0]
+    assert bool((P >= 0).all()) and abs(float(P.sum()) - total) <= 1e-9 * total
+    assert float(c.abs().max()) <= 30.0
+    g.close()
