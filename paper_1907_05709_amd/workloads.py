@@ -246,6 +246,59 @@ def case_homogeneous(n: int = 32, dx: float = 1e-3, power: float = 20.0,
                 needle, dt, n_steps, seed)
 
 
+# The paper's own liver model and evaluation setting (Sec. "Specialized
+# Methods for Liver Ablation Simulation": the constants listed after Eq.
+# (2675-eq1_Kath); Sec. "Evaluation Methods": 0.5 mm voxels, dt 0.1 s, a
+# hemispherical electrode tip held at 90 or 60 degC).  The planning
+# workloads above use the configured values instead.
+PAPER_K, PAPER_RHO, PAPER_C = 0.52, 1079.0, 3540.0
+PAPER_WB, PAPER_CB = 16.687, 3617.0     # w_b [kg/m^3/s] and c_b [J/kg/K]
+PAPER_QM = 10714.0                       # metabolic heat, W/m^3
+PAPER_R = 8.31                           # gas constant as printed
+LABEL_TIP = 2                            # class of the held electrode tip (paper mode)
+
+
+def paper_tip_offsets() -> np.ndarray:
+    """Voxel offsets (i, j, k) of the hemispherical electrode tip, 5 x 5 x 3
+    voxels: (i / 2.5)^2 + (j / 2.5)^2 + (k / 3)^2 <= 1 with k = 0, 1, 2 (the
+    flat face at k = 0, the dome toward +z)."""
+    r = range(-2, 3)
+    return np.array([(i, j, k) for i in r for j in r for k in range(3)
+                     if (i / 2.5) ** 2 + (j / 2.5) ** 2 + (k / 3.0) ** 2 <= 1.0], dtype=np.int64)
+
+
+def case_paper_mode(tip_c: float = 90.0, n: int = 48, dx: float = 0.5e-3, dt: float = 0.1,
+                    n_steps: int = 600, seed: int = 6000) -> Case:
+    """The paper's evaluation setting: homogeneous liver with the paper's
+    constants (perfusion h = w_b c_b, metabolic heat Q_m, R as printed), a
+    hemispherical tip of 5 x 5 x 3 voxels held at tip_c degC at the grid
+    centre (class LABEL_TIP: held, no damage), no RF source, everything else
+    starting at 37 degC with a held 37 degC outer layer.  Probe points:
+    paper_probes()."""
+    shape = (n, n, n)
+    labels = _with_boundary(np.full(shape, LABEL_LIVER, dtype=np.uint8))
+    c = n // 2
+    for i, j, k in paper_tip_offsets():
+        labels[c + i, c + j, c + k] = LABEL_TIP
+    h = PAPER_WB * PAPER_CB
+    tissue = [Tissue(PAPER_K, PAPER_RHO, PAPER_C, 0.0, 0.0, 37.0, fixed=1, tissue=0),
+              Tissue(PAPER_K, PAPER_RHO, PAPER_C, h, PAPER_QM),
+              Tissue(PAPER_K, PAPER_RHO, PAPER_C, 0.0, 0.0, float(tip_c), fixed=1, tissue=0)]
+    none = Needle(np.array([0], np.int32), np.zeros((0, 3)), np.zeros(0), dx, "none")
+    return Case(f"paper_tip{tip_c:g}", shape, (dx, dx, dx), labels, tissue, none, dt, n_steps,
+                seed, gas_r=PAPER_R, meta={"tip_c": float(tip_c)})
+
+
+def paper_probes(case: Case, distances_mm=(2.5, 5.0)) -> dict:
+    """Voxel index of each probe: on the tip axis, the given distance beyond
+    the dome's apex voxel (distances in whole voxels of the case's spacing)."""
+    n = case.shape[0]
+    c = n // 2
+    apex = c + int(paper_tip_offsets()[:, 2].max())
+    dz = case.spacing[2] * 1e3
+    return {d: (c, c, apex + int(round(d / dz))) for d in distances_mm}
+
+
 def case_straight(n: int = 128, dx: float = 0.5e-3, dt: float = 0.01,
                   n_steps: int = 1000, seed: int = 2000) -> Case:
     """Heterogeneous liver (tumour r ~ U(6,10) mm centred <= 5 mm from the tip,

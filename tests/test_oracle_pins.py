@@ -428,3 +428,22 @@ def test_bspline_partition_of_unity_and_transpose():
     f = np.log(O.bspline_field(shape, lin))
     ux = np.arange(shape[0]) * (m - 3) / (shape[0] - 1)
     assert np.allclose(f, ux[:, None, None], atol=1e-13)
+
+
+def test_paper_mode_workload_uses_the_printed_constants():
+    """The paper-mode generator's constants are the values the paper prints
+    (fixture with its citation), its tip is 5 x 5 x 3 voxels, and its dt is
+    inside the stability bound the oracle computes."""
+    with open(os.path.join(GOLDEN, "paper_constants.json")) as f:
+        pc = json.load(f)
+    assert (W.PAPER_K, W.PAPER_RHO, W.PAPER_C) == (pc["k_liver_W_mK"], pc["rho_liver_kg_m3"],
+                                                  pc["c_liver_J_kgK"])
+    assert (W.PAPER_WB, W.PAPER_CB, W.PAPER_QM, W.PAPER_R) == (
+        pc["w_b_kg_m3s"], pc["c_b_J_kgK"], pc["Q_m_W_m3"], pc["R_J_molK"])
+    off = W.paper_tip_offsets()
+    assert np.ptp(off[:, 0]) + 1 == 5 and np.ptp(off[:, 1]) + 1 == 5 and np.ptp(off[:, 2]) + 1 == 3
+    for tip in pc["eval_tip_degC"]:
+        case = W.case_paper_mode(tip_c=tip, n=24)
+        assert case.spacing[0] * 1e3 == pc["eval_voxel_mm"] and case.dt == pc["eval_dt_s"]
+        assert case.dt < O.dt_max(case)
+        assert case.tissue[W.LABEL_TIP].t_fixed == tip
