@@ -299,6 +299,46 @@ def paper_probes(case: Case, distances_mm=(2.5, 5.0)) -> dict:
     return {d: (c, c, apex + int(round(d / dz))) for d in distances_mm}
 
 
+def breathing_field(shape, spacing, amplitude_m: float = 5e-3, seed: int = 7000) -> np.ndarray:
+    """Synthetic inverse breathing displacement v [3, nx, ny, nz] (float32,
+    metres), a stand-in for the 4D-CT registration fields the paper uses:
+    mostly cranio-caudal (z), largest mid-grid, zero normal motion at the
+    walls, smooth enough to stay diffeomorphic (|dv/dx| below 0.5 at 5 mm over
+    a few centimetres).  A seeded random phase varies the pattern."""
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=3)
+    u = [np.linspace(0.0, 1.0, n) for n in shape]
+    X, Y, Z = np.meshgrid(*u, indexing="ij")
+    bump = np.sin(np.pi * X) * np.sin(np.pi * Y)
+    vz = amplitude_m * bump * np.sin(np.pi * Z)
+    vx = 0.3 * amplitude_m * np.sin(np.pi * X) * np.sin(2 * np.pi * Y + ph[0]) * np.sin(np.pi * Z)
+    vy = 0.2 * amplitude_m * np.sin(2 * np.pi * X + ph[1]) * np.sin(np.pi * Y) * np.sin(np.pi * Z)
+    return np.stack([vx, vy, vz]).astype(np.float32)
+
+
+def breathing_surrogate(t: float, period_s: float = 4.0) -> float:
+    """Surrogate signal of a regular breathing cycle in [0, 1]."""
+    return float(np.sin(np.pi * t / period_s) ** 2)
+
+
+def hot_field(shape, spacing, peak_c: float = 900.0, sigma_m: float = 4e-3,
+              seed: int = 7100) -> np.ndarray:
+    """Synthetic temperature image (degC, float64): 37 degC plus a few
+    Gaussian hot spots up to peak_c, steep enough (hundreds of K per voxel
+    near the peaks) to exercise an interpolation."""
+    rng = np.random.default_rng(seed)
+    axes = voxel_axes(shape, spacing)
+    X, Y, Z = np.meshgrid(*axes, indexing="ij")
+    T = np.full(shape, 37.0)
+    half = np.array([(n - 1) * d / 2.0 for n, d in zip(shape, spacing)])
+    for k in range(3):
+        c = rng.uniform(-0.5 * half, 0.5 * half)
+        a = peak_c - 37.0 if k == 0 else rng.uniform(50.0, 300.0)
+        s = sigma_m * rng.uniform(0.5, 1.5)
+        T += a * np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) / (2 * s * s))
+    return T
+
+
 def case_straight(n: int = 128, dx: float = 0.5e-3, dt: float = 0.01,
                   n_steps: int = 1000, seed: int = 2000) -> Case:
     """Heterogeneous liver (tumour r ~ U(6,10) mm centred <= 5 mm from the tip,
