@@ -1,6 +1,6 @@
 """Benchmark of the explicit bioheat stepper on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2|3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2|3|4|5|6]
 
 A bench step is one rfa_step call that advances the workload by its full
 simulated duration (all per-step work: conduction, perfusion, RF source,
@@ -8,7 +8,10 @@ held voxels, float-float Euler update, Arrhenius damage and latch,
 per-step diagnostics), with the grid's inputs resident in HBM.  The default
 workload is the single-instance heterogeneous case: 128^3 voxels at 0.5 mm,
 liver with a tumour and 3-6 vessels, straight needle, 1000 steps of
-0.01 s.  --config 3 runs the 256^3 umbrella-needle case (6000 steps).
+0.01 s.  --config 3 runs the 256^3 umbrella-needle case (6000 steps);
+--config 4 the batched sweep, --config 5 the differentiation workload
+(forward + adjoint) and --config 6 the breathing-motion view of a 256^3
+temperature image (one warp per step).
 
 Prints one JSON line: voxel-updates/s over the timed steps, the step
 kernel's roofline (algorithmic bytes per launch over its HIP-event-timed
@@ -146,6 +149,8 @@ def main():
         return bench_batch(args)
     if args.config == 5:
         return bench_adjoint(args)
+    if args.config == 6:
+        return bench_warp(args)
     case, name = workload(args.config)
     if args.time_steps > 0:
         case.n_steps = args.time_steps
@@ -383,6 +388,82 @@ def bench_adjoint(args):
                      "bytes_per_launch": bytes_per_launch},
     }
     print(json.dumps(out), flush=True)
+
+
+WARP_BYTES_PER_VOXEL = 20   # displacement (3 x 4) + source image (4) + output (4)
+
+
+def bench_warp(args):
+    """Breathing-motion view (Eq. (eq:breathing)) of a 256^3 temperature
+    image at 0.5 mm: synthetic inverse-motion field of 12 mm cranio-caudal
+    amplitude, one bench step = one rfa_warp of the whole grid at the
+    surrogate value of the next frame of a 4 s breathing cycle (25 frames/s),
+    inputs and output resident in HBM.  value = output voxels per second."""
+    import numpy as np
+    import torch
+    from paper_1907_05709_amd import rfa
+    from paper_1907_05709_amd import workloads as W
+
+    shape, spacing = (256, 256, 256), (0.5e-3,) * 3
+    n = int(np.prod(shape))
+    T = W.hot_field(shape, spacing)
+    v_host = W.breathing_field(shape, spacing, amplitude_m=12e-3)
+    g = rfa.Grid(shape, spacing, device=True)
+    g.set_tissue(torch.ones(shape, dtype=torch.uint8, device="cuda"), W.standard_tissue())
+    g.set_temperature(torch.from_numpy(T).cuda())
+    v = torch.from_numpy(v_host).cuda()
+    out = torch.empty(shape, dtype=torch.float32, device="cuda")
+    betas = [W.breathing_surrogate(k / 25.0) for k in range(args.warmup + args.steps)]
+    for k in range(args.warmup):
+        g.warp(v, betas[k], out=out)
+    stream = torch.cuda.current_stream()    # the grid launches on this stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for k in range(args.warmup, args.warmup + args.steps):
+        g.warp(v, betas[k], out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    avg_ms = e0.elapsed_time(e1) / args.steps
+    g.close()
+    value = n * args.steps / wall / 1e9
+    bytes_per_launch = WARP_BYTES_PER_VOXEL * n
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    out_json = {
+        "metric": "GVoxel/s of breathing-motion temperature views",
+        "value": round(value, 3),
+        "unit": "GVoxel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "breathing-motion warp: 256^3 @0.5mm temperature image (hot "
+                               "spots to 900 degC), 12 mm synthetic inverse-motion field, "
+                               "trilinear, one frame per step"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "kernel": "k_warp",
+                     "avg_launch_us": round(avg_ms * 1e3, 3),
+                     "bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu:
+        from oracle.warp import warp as warp_oracle
+        frames = max(1, args.cpu_steps or 3)
+        t0 = time.perf_counter()
+        for k in range(frames):
+            warp_oracle(T, v_host, spacing, betas[k])
+        dt = time.perf_counter() - t0
+        out_json["cpu_baseline"] = {
+            "value": n * frames / dt / 1e9, "unit": "GVoxel/s", "cores": 1, "kind": "oracle",
+            "sample": f"{frames} full 256^3 frames, FP64 numpy, {dt:.1f} s wall"}
+    print(json.dumps(out_json), flush=True)
 
 
 if __name__ == "__main__":

@@ -187,6 +187,20 @@ rfa_status rfa_get_temperature(rfa_grid g, double* t_C, float* hi, float* lo);
  * latches are kept.  Held voxels take the given values as well. */
 rfa_status rfa_set_temperature(rfa_grid g, const double* t_C);
 
+/* Breathing-motion view of the current temperature (Eq. (eq:breathing)):
+ * out[x] = T(x + beta v(x)) in degC, T taken trilinearly between voxel
+ * centres from the float excess-temperature state (the hi word), sample
+ * positions beyond the grid taken on its walls.  v: [3][nx*ny*nz] float, the
+ * x, y and z components of the inverse breathing displacement in metres;
+ * beta: the breathing surrogate (finite); out: [nx*ny*nz] float, caller
+ * owned.  v and out are host or device pointers per inputs_on_device; on
+ * the host path a non-finite displacement gives RFA_ERR_ARG, on the device
+ * path it is not checked and samples a wall.  The state is not changed.
+ * kernel_ms (may be NULL): if given, the call synchronises and returns the
+ * warp kernel's duration measured with HIP events on the grid's stream.
+ * Grids of 2^31 voxels or more give RFA_ERR_ARG. */
+rfa_status rfa_warp(rfa_grid g, const float* v, double beta, float* out, double* kernel_ms);
+
 /* Serialise / restore the full dynamic state (temperature, damage, latches,
  * step count) with a checksum.  bytes: in = capacity, out = size needed
  * (call with buf == NULL to query).  A buffer from another grid shape or a

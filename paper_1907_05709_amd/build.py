@@ -21,7 +21,7 @@ OUT = os.path.join(PKG, "librfa.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 SOURCES = ["rfa_api.hip", "rfa_kernels.hip", "rfa_step.hip", "rfa_tiled.hip", "rfa_tiled2.hip",
            "rfa_wide.hip",
-           "rfa_adjoint.hip"]
+           "rfa_adjoint.hip", "rfa_warp.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -19,6 +19,7 @@
 #include "rfa_kernels.h"
 #include "rfa_adjoint.h"
 #include "rfa_step.h"
+#include "rfa_warp.h"
 
 using namespace rfa;
 
@@ -878,6 +879,57 @@ rfa_status rfa_set_temperature(rfa_grid g, const double* t_C) {
   if (e != hipSuccess) return fail(RFA_ERR_HIP, "set_temperature: %s", hipGetErrorString(e));
   g->energy_valid = false;
   ++g->version;
+  return RFA_OK;
+}
+
+rfa_status rfa_warp(rfa_grid g, const float* v, double beta, float* out, double* kernel_ms) {
+  if (!g || !v || !out) return fail(RFA_ERR_ARG, "grid, v and out are required");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "no tissue");
+  if (!std::isfinite(beta)) return fail(RFA_ERR_ARG, "beta not finite");
+  const size_t n = g->g.n();
+  if (n >= (size_t(1) << 31)) return fail(RFA_ERR_ARG, "warp needs fewer than 2^31 voxels");
+  const bool dev = g->opt.inputs_on_device != 0;
+  if (!dev) {
+    for (size_t p = 0; p < 3 * n; ++p)
+      if (!std::isfinite(v[p])) return fail(RFA_ERR_ARG, "displacement not finite at %zu", p);
+  }
+  // beta / spacing in FP64, rounded once: s_a = scale_a * v_a in voxels
+  const float sx = (float)(beta / g->dx), sy = (float)(beta / g->dy), sz = (float)(beta / g->dz);
+  float* dv = const_cast<float*>(v);
+  float* dout = out;
+  if (!dev) {
+    rfa_status s = dmalloc(&dv, 3 * n);
+    if (s != RFA_OK) return s;
+    if ((s = dmalloc(&dout, n)) != RFA_OK) {
+      (void)hipFree(dv);
+      return s;
+    }
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  if (!dev) e = hipMemcpyAsync(dv, v, 3 * n * sizeof(float), hipMemcpyHostToDevice, g->st);
+  if (e == hipSuccess && kernel_ms) {
+    e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], g->st);
+  }
+  if (e == hipSuccess) e = launch_warp(g->g, g->hi[g->cur], dv, sx, sy, sz, dout, g->st);
+  if (e == hipSuccess && kernel_ms) e = hipEventRecord(ev[1], g->st);
+  if (e == hipSuccess && !dev)
+    e = hipMemcpyAsync(out, dout, n * sizeof(float), hipMemcpyDeviceToHost, g->st);
+  if (e == hipSuccess && (kernel_ms || !dev)) e = hipStreamSynchronize(g->st);
+  if (e == hipSuccess && kernel_ms) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    *kernel_ms = ms;
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (!dev) {
+    (void)hipFree(dv);
+    (void)hipFree(dout);
+  }
+  if (e != hipSuccess) return fail(RFA_ERR_HIP, "warp: %s", hipGetErrorString(e));
   return RFA_OK;
 }
 

@@ -83,6 +83,7 @@ _SIGS = {
     "rfa_get_plan": [C.c_void_p] + [C.POINTER(C.c_int)] * 6,
     "rfa_tune": [C.c_void_p, C.c_double, C.c_int],
     "rfa_copy_bandwidth": [C.c_size_t, C.c_int, C.POINTER(C.c_double)],
+    "rfa_warp": [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.POINTER(C.c_double)],
     "rfa_set_perfusion_bspline": [C.c_void_p, C.c_int, C.c_void_p],
     "rfa_reset_state": [C.c_void_p],
     "rfa_set_tine_powers": [C.c_void_p, C.POINTER(C.c_double)],
@@ -269,6 +270,14 @@ def rfa_get_plan(g):
 
 def rfa_tune(g, dt: float, reps: int = 20):
     _check(lib().rfa_tune(g, float(dt), int(reps)))
+
+
+def rfa_warp(g, v_ptr, beta: float, out_ptr, timed: bool = False):
+    """Breathing-motion view of the temperature; returns the kernel time in
+    ms when timed, else None."""
+    ms = C.c_double(0.0)
+    _check(lib().rfa_warp(g, v_ptr, float(beta), out_ptr, C.byref(ms) if timed else None))
+    return ms.value if timed else None
 
 
 def rfa_copy_bandwidth(nbytes: int, reps: int = 20) -> float:
@@ -497,6 +506,20 @@ class Grid:
         else:
             a = np.ascontiguousarray(t, dtype=np.float64)
             rfa_set_temperature(self.h, _ptr(a, False, np.float64))
+
+    def warp(self, v, beta: float, out=None, timed: bool = False):
+        """Temperature (degC, float) seen through the inverse breathing
+        displacement beta * v, v of shape (3, nx, ny, nz) in metres.  Returns
+        out, or (out, kernel_ms) when timed."""
+        if tuple(v.shape) != (3,) + self.shape:
+            raise ValueError(f"v must have shape {(3,) + self.shape}")
+        if out is None:
+            out = self._alloc(np.float32)
+        if not self.device:
+            v = np.ascontiguousarray(v, dtype=np.float32)
+        ms = rfa_warp(self.h, _ptr(v, self.device, np.float32),
+                      beta, _ptr(out, self.device, np.float32, True), timed)
+        return (out, ms) if timed else out
 
     def damage(self):
         mask, om = self._alloc(np.uint8), self._alloc(np.float32)
