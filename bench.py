@@ -50,6 +50,7 @@ KERNEL_SOURCES = {
     "k_step_wide": ("rfa_wide.hip",) + _SHARED,
     "k_step_tiled": ("rfa_tiled.hip", "rfa_tiled.h") + _SHARED,
     "k_step_batch": ("rfa_tiled.hip", "rfa_tiled.h") + _SHARED,
+    "k_warp": ("rfa_warp.hip", "rfa_warp.h") + _SHARED,
 }
 
 
@@ -91,10 +92,10 @@ def workload(config: int):
     return case, name
 
 
-def traffic_record(config: int, plan: dict, kernel: str):
+def traffic_record(config: int, plan: dict, kernel: str, name: str = ""):
     """Bytes per launch below L2 from committed rocprofv3 counter summaries,
     if they were taken on the kernel's current sources and launch plan."""
-    path = os.path.join(ROOT, "profiles", f"traffic_step_config{config}.json")
+    path = os.path.join(ROOT, "profiles", name or f"traffic_step_config{config}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -391,14 +392,17 @@ def bench_adjoint(args):
 
 
 WARP_BYTES_PER_VOXEL = 20   # displacement (3 x 4) + source image (4) + output (4)
+WARP_PLAN = {"threads": 256, "x_voxels_per_thread": 4}
+WARP_FRAMES_PER_CYCLE = 100
 
 
 def bench_warp(args):
     """Breathing-motion view (Eq. (eq:breathing)) of a 256^3 temperature
-    image at 0.5 mm: synthetic inverse-motion field of 12 mm cranio-caudal
-    amplitude, one bench step = one rfa_warp of the whole grid at the
-    surrogate value of the next frame of a 4 s breathing cycle (25 frames/s),
-    inputs and output resident in HBM.  value = output voxels per second."""
+    image at 0.5 mm through a synthetic inverse-motion field of 12 mm
+    cranio-caudal amplitude.  One bench step = one 4 s breathing cycle shown
+    at 25 frames/s: 100 rfa_warp calls over the whole grid, the surrogate
+    going 0 -> 1 -> 0, inputs and output resident in HBM.  value = output
+    voxels per second."""
     import numpy as np
     import torch
     from paper_1907_05709_amd import rfa
@@ -413,22 +417,29 @@ def bench_warp(args):
     g.set_temperature(torch.from_numpy(T).cuda())
     v = torch.from_numpy(v_host).cuda()
     out = torch.empty(shape, dtype=torch.float32, device="cuda")
-    betas = [W.breathing_surrogate(k / 25.0) for k in range(args.warmup + args.steps)]
-    for k in range(args.warmup):
-        g.warp(v, betas[k], out=out)
+    betas = [W.breathing_surrogate(f / 25.0) for f in range(WARP_FRAMES_PER_CYCLE)]
+
+    def cycle():
+        for b in betas:
+            g.warp(v, b, out=out)
+
+    for _ in range(args.warmup):
+        cycle()
     stream = torch.cuda.current_stream()    # the grid launches on this stream
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    for k in range(args.warmup, args.warmup + args.steps):
-        g.warp(v, betas[k], out=out)
+    for _ in range(args.steps):
+        cycle()
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    avg_ms = e0.elapsed_time(e1) / args.steps
+    launches = args.steps * len(betas)
+    avg_ms = e0.elapsed_time(e1) / launches
+    copy_gbps = rfa.rfa_copy_bandwidth(1 << 30, 10)
     g.close()
-    value = n * args.steps / wall / 1e9
+    value = n * launches / wall / 1e9
     bytes_per_launch = WARP_BYTES_PER_VOXEL * n
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     out_json = {
@@ -446,23 +457,27 @@ def bench_warp(args):
         "data": "synthetic",
         "config": {"workload": "breathing-motion warp: 256^3 @0.5mm temperature image (hot "
                                "spots to 900 degC), 12 mm synthetic inverse-motion field, "
-                               "trilinear, one frame per step"},
+                               "trilinear; one step = one 4 s breathing cycle, 100 frames"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": None, "kernel": "k_warp",
-                     "avg_launch_us": round(avg_ms * 1e3, 3),
-                     "bytes_per_launch": bytes_per_launch},
+                     "traffic": traffic_record(6, WARP_PLAN, "k_warp",
+                                               "traffic_warp_breathing256.json"),
+                     "kernel": "k_warp", "avg_launch_us": round(avg_ms * 1e3, 3),
+                     "launches_timed": launches,
+                     "bytes_per_launch": bytes_per_launch,
+                     "copy_ceiling_GBps": round(copy_gbps, 1)},
     }
     if not args.no_cpu:
         from oracle.warp import warp as warp_oracle
-        frames = max(1, args.cpu_steps or 3)
+        frames = max(1, args.cpu_steps or 8)
         t0 = time.perf_counter()
         for k in range(frames):
-            warp_oracle(T, v_host, spacing, betas[k])
+            warp_oracle(T, v_host, spacing, betas[(k * 37) % len(betas)])
         dt = time.perf_counter() - t0
         out_json["cpu_baseline"] = {
             "value": n * frames / dt / 1e9, "unit": "GVoxel/s", "cores": 1, "kind": "oracle",
-            "sample": f"{frames} full 256^3 frames, FP64 numpy, {dt:.1f} s wall"}
+            "sample": f"{frames} full 256^3 frames at spread phases of the cycle, FP64 "
+                      f"numpy, {dt:.1f} s wall"}
     print(json.dumps(out_json), flush=True)
 
 

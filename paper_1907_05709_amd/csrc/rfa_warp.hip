@@ -2,12 +2,21 @@
 //
 // The simulated temperature is shown in the breathing phase given by a
 // surrogate signal beta(t) by pulling it back through the inverse motion
-// field (Eq. (eq:breathing)): T_view(x) = T(x + beta v(x)).  One thread per
-// output voxel; z is the fastest index, so a wave covers 64 consecutive z
-// voxels and, the motion being smooth, its eight corner gathers fall on a few
-// contiguous cache lines of four source rows.  Bytes that must move per
-// voxel: the three displacement components, one output, and the source image
-// once (20 bytes); the 2 x 2 corner re-reads are served by the caches.
+// field (Eq. (eq:breathing)): T_view(x) = T(x + beta v(x)).  z is the fastest
+// index, so a wave covers 64 consecutive z voxels and, the motion being
+// smooth, its corner gathers fall on a few contiguous cache lines of four
+// source rows.  Bytes that must move per voxel: the three displacement
+// components, one output, and the source image once (20 bytes); the 2 x 2
+// corner re-reads are served by the caches.
+//
+// Launch shape (measured on 256^3 at 0.5 mm with a 12 mm field): each
+// thread takes kVx voxels adjacent in x, which share source rows and put
+// four independent gather chains in flight (55 us against 83 us for one
+// voxel per thread); the two z corners of a row are one 8-byte load (a
+// multi-dword load needs only 4-byte alignment); the displacement is read
+// with the ordinary cache policy, so the part of it that stays in the
+// last-level cache between frames is reused (non-temporal reads cost 25 %),
+// and the output is stored non-temporally (write-back stores cost 35 %).
 #include "rfa_warp.h"
 #include "rfa_tile_common.h"
 
@@ -15,6 +24,10 @@ namespace rfa {
 namespace {
 
 constexpr int kWarpThreads = 256;
+constexpr int kVx = 4;
+
+// Two consecutive floats, 4-byte aligned.
+typedef float pair_f32 __attribute__((ext_vector_type(2), aligned(4)));
 
 // Split the position i + s (voxels) into a base index k in [0, n - 2] and a
 // fraction f in [0, 1], positions beyond the walls taken at the wall.  f is
@@ -43,31 +56,48 @@ __device__ __forceinline__ float lerp(float a, float b, float t) {
 __global__ __launch_bounds__(kWarpThreads) void k_warp(
     const float* __restrict__ hi, const float* __restrict__ vx, const float* __restrict__ vy,
     const float* __restrict__ vz, float* __restrict__ out, int nx, int ny, int nz,
-    unsigned n, float cx, float cy, float cz) {
+    unsigned n_threads, float cx, float cy, float cz) {
   const int wg = tile::remap_xcd(blockIdx.x, gridDim.x);
   const unsigned q = (unsigned)wg * kWarpThreads + threadIdx.x;
-  if (q >= n) return;
+  if (q >= n_threads) return;
   const unsigned row = q / (unsigned)nz;
   const int z = (int)(q - row * (unsigned)nz);
-  const int x = (int)(row / (unsigned)ny);
-  const int y = (int)(row - (unsigned)x * (unsigned)ny);
-
-  int kx, ky, kz;
-  float fx, fy, fz;
-  locate(cx * __builtin_nontemporal_load(vx + q), x, nx, kx, fx);
-  locate(cy * __builtin_nontemporal_load(vy + q), y, ny, ky, fy);
-  locate(cz * __builtin_nontemporal_load(vz + q), z, nz, kz, fz);
-
+  const int xg = (int)(row / (unsigned)ny);  // group of kVx x planes
+  const int y = (int)(row - (unsigned)xg * (unsigned)ny);
   const unsigned sy = (unsigned)nz, sx = (unsigned)ny * (unsigned)nz;
-  const float* p = hi + ((unsigned)kx * sx + (unsigned)ky * sy + (unsigned)kz);
-  const float c000 = p[0], c001 = p[1];
-  const float c010 = p[sy], c011 = p[sy + 1];
-  const float c100 = p[sx], c101 = p[sx + 1];
-  const float c110 = p[sx + sy], c111 = p[sx + sy + 1];
-  const float e00 = lerp(c000, c001, fz), e01 = lerp(c010, c011, fz);
-  const float e10 = lerp(c100, c101, fz), e11 = lerp(c110, c111, fz);
-  const float d0 = lerp(e00, e01, fy), d1 = lerp(e10, e11, fy);
-  __builtin_nontemporal_store(37.0f + lerp(d0, d1, fx), out + q);
+  const unsigned yz = (unsigned)y * sy + (unsigned)z;
+
+  // planes past nx (last group) repeat plane nx - 1 and are not stored
+  float ux[kVx], uy[kVx], uz[kVx];
+#pragma unroll
+  for (int j = 0; j < kVx; ++j) {
+    const unsigned o = (unsigned)min(xg * kVx + j, nx - 1) * sx + yz;
+    ux[j] = vx[o];
+    uy[j] = vy[o];
+    uz[j] = vz[o];
+  }
+  float r[kVx];
+#pragma unroll
+  for (int j = 0; j < kVx; ++j) {
+    int kx, ky, kz;
+    float fx, fy, fz;
+    locate(cx * ux[j], min(xg * kVx + j, nx - 1), nx, kx, fx);
+    locate(cy * uy[j], y, ny, ky, fy);
+    locate(cz * uz[j], z, nz, kz, fz);
+    const float* p = hi + ((unsigned)kx * sx + (unsigned)ky * sy + (unsigned)kz);
+    const pair_f32 c00 = *(const pair_f32*)p;
+    const pair_f32 c01 = *(const pair_f32*)(p + sy);
+    const pair_f32 c10 = *(const pair_f32*)(p + sx);
+    const pair_f32 c11 = *(const pair_f32*)(p + sx + sy);
+    const float e00 = lerp(c00.x, c00.y, fz), e01 = lerp(c01.x, c01.y, fz);
+    const float e10 = lerp(c10.x, c10.y, fz), e11 = lerp(c11.x, c11.y, fz);
+    r[j] = lerp(lerp(e00, e01, fy), lerp(e10, e11, fy), fx);
+  }
+#pragma unroll
+  for (int j = 0; j < kVx; ++j) {
+    const int x = xg * kVx + j;
+    if (x < nx) __builtin_nontemporal_store(37.0f + r[j], out + ((unsigned)x * sx + yz));
+  }
 }
 
 }  // namespace
@@ -77,9 +107,10 @@ hipError_t launch_warp(Grid3 g, const float* hi, const float* v, float scale_x, 
   const size_t n = g.n();
   if (n == 0) return hipSuccess;
   if (n >= (size_t(1) << 31) || g.nx < 2 || g.ny < 2 || g.nz < 2) return hipErrorInvalidValue;
-  const unsigned blocks = (unsigned)((n + kWarpThreads - 1) / kWarpThreads);
+  const size_t threads = (size_t)((g.nx + kVx - 1) / kVx) * g.ny * g.nz;
+  const unsigned blocks = (unsigned)((threads + kWarpThreads - 1) / kWarpThreads);
   hipLaunchKernelGGL(k_warp, dim3(blocks), dim3(kWarpThreads), 0, st, hi, v, v + n, v + 2 * n,
-                     out, g.nx, g.ny, g.nz, (unsigned)n, scale_x, scale_y, scale_z);
+                     out, g.nx, g.ny, g.nz, (unsigned)threads, scale_x, scale_y, scale_z);
   return hipGetLastError();
 }
 
