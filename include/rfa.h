@@ -219,6 +219,13 @@ rfa_status rfa_get_step_count(rfa_grid g, long long* steps);
 rfa_status rfa_kernel_stats(rfa_grid g, double* kernel_ms, long long* launches,
                             long long* voxel_steps);
 
+/* Adjoint-kernel timing accumulated since the last call (requires
+ * rfa_options.time_kernels; kept-trajectory adjoints only, ckpt_every = 0):
+ * total milliseconds measured with one pair of HIP events around each
+ * adjoint's back-to-back step launches, and the number of those launches.
+ * Resets the counters.  Either argument may be NULL. */
+rfa_status rfa_adjoint_kernel_stats(rfa_grid g, double* kernel_ms, long long* launches);
+
 /* Current launch plan: kernel (1 reference, 2 tiled), steps per launch,
  * tile rows, x planes per work-group, work-groups per launch, z voxels per
  * lane. */

@@ -137,6 +137,9 @@ struct rfa_grid_s {
   double kernel_ms = 0.0;
   long long kernel_launches = 0;
   long long kernel_voxel_steps = 0;
+  // adjoint-kernel timing (kept-trajectory schedule)
+  double adj_kernel_ms = 0.0;
+  long long adj_kernel_launches = 0;
 };
 
 namespace {
@@ -1028,6 +1031,15 @@ rfa_status rfa_get_step_count(rfa_grid g, long long* steps) {
   return RFA_OK;
 }
 
+rfa_status rfa_adjoint_kernel_stats(rfa_grid g, double* kernel_ms, long long* launches) {
+  if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
+  if (kernel_ms) *kernel_ms = g->adj_kernel_ms;
+  if (launches) *launches = g->adj_kernel_launches;
+  g->adj_kernel_ms = 0.0;
+  g->adj_kernel_launches = 0;
+  return RFA_OK;
+}
+
 rfa_status rfa_kernel_stats(rfa_grid g, double* kernel_ms, long long* launches,
                             long long* voxel_steps) {
   if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
@@ -1376,12 +1388,15 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
   HIP_TRY(hipMemcpyAsync(g->lab_scratch, g->lab, n, hipMemcpyDeviceToDevice, g->st));
   if ((s = prepare_dt(g, g->adj_dt)) != RFA_OK) return s;
   const StepConst K = step_const(g, g->adj_dt);
-  // adjoint schedule: the tiled kernel (4 rows, about 1024 work-groups)
-  // unless the grid asked for the reference kernels
+  // adjoint schedule: the tiled kernel (8 rows, x chunks sized for about
+  // one work-group per compute unit; at 128^3: 256 work-groups of 16 planes,
+  // 8 % faster than 1024 work-groups of 4 rows x 8 planes) unless the grid
+  // asked for the reference kernels
+  constexpr int adj_ty = 8;
   int adj_xc = 4;
   {
-    const int tiles = ((g->g.nz + 63) / 64) * ((g->g.ny + 3) / 4);
-    const int chunks = std::max(1, (1024 + tiles - 1) / tiles);
+    const int tiles = ((g->g.nz + 63) / 64) * ((g->g.ny + adj_ty - 1) / adj_ty);
+    const int chunks = std::max(1, (256 + tiles - 1) / tiles);
     adj_xc = std::min(g->g.nx, std::max(4, (g->g.nx + chunks - 1) / chunks));
   }
   const bool tiled_adj = g->plan.kind != kStepNaive && adjoint_tiled_fits(g->g, adj_xc);
@@ -1399,12 +1414,27 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
     a.sacc = sacc;
     a.facc = facc;
     lc = 1 - lc;
-    return tiled_adj ? launch_adjoint_tiled(g->g, 4, adj_xc, a, K, g->st)
+    return tiled_adj ? launch_adjoint_tiled(g->g, adj_ty, adj_xc, a, K, g->st)
                      : launch_adjoint_step(g->g, a, K, g->st);
   };
-  if (every == 0)  // the forward kept every theta^t: no recomputation
+  if (every == 0) {  // the forward kept every theta^t: no recomputation
+    // with time_kernels, one event pair brackets the back-to-back launches
+    const bool timed = g->opt.time_kernels != 0 && g->adj_steps > 0;
+    if (timed) {
+      if ((s = ensure_events(g, 2)) != RFA_OK) return s;
+      HIP_TRY(hipEventRecord(g->events[0], g->st));
+    }
     for (int t = g->adj_steps - 1; t >= 0; --t)
       HIP_TRY(adjoint_step(g->traj + (size_t)t * n));
+    if (timed) {
+      float ms = 0.0f;
+      HIP_TRY(hipEventRecord(g->events[1], g->st));
+      HIP_TRY(hipEventSynchronize(g->events[1]));
+      HIP_TRY(hipEventElapsedTime(&ms, g->events[0], g->events[1]));
+      g->adj_kernel_ms += ms;
+      g->adj_kernel_launches += g->adj_steps;
+    }
+  }
   for (int seg = g->adj_nckpt - 1; seg >= 0; --seg) {
     const int k = std::min(every, g->adj_steps - seg * every);
     const float* c = g->ckpt + (size_t)seg * 2 * n;

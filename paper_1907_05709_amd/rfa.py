@@ -83,6 +83,7 @@ _SIGS = {
     "rfa_get_plan": [C.c_void_p] + [C.POINTER(C.c_int)] * 6,
     "rfa_tune": [C.c_void_p, C.c_double, C.c_int],
     "rfa_copy_bandwidth": [C.c_size_t, C.c_int, C.POINTER(C.c_double)],
+    "rfa_adjoint_kernel_stats": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
     "rfa_warp": [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.POINTER(C.c_double)],
     "rfa_set_perfusion_bspline": [C.c_void_p, C.c_int, C.c_void_p],
     "rfa_reset_state": [C.c_void_p],
@@ -278,6 +279,13 @@ def rfa_warp(g, v_ptr, beta: float, out_ptr, timed: bool = False):
     ms = C.c_double(0.0)
     _check(lib().rfa_warp(g, v_ptr, float(beta), out_ptr, C.byref(ms) if timed else None))
     return ms.value if timed else None
+
+
+def rfa_adjoint_kernel_stats(g):
+    """(milliseconds, launches) of adjoint kernels timed since the last call."""
+    ms, n = C.c_double(0.0), C.c_longlong(0)
+    _check(lib().rfa_adjoint_kernel_stats(g, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
 
 
 def rfa_copy_bandwidth(nbytes: int, reps: int = 20) -> float:
@@ -569,6 +577,9 @@ class Grid:
         rfa_adjoint(self.h, wp, dP, dc,
                     None if dperf is None else _ptr(dperf, self.device, np.float32, True))
         return dP, dc, dperf
+
+    def adjoint_kernel_stats(self):
+        return rfa_adjoint_kernel_stats(self.h)
 
     def plan(self) -> dict:
         return rfa_get_plan(self.h)

@@ -213,3 +213,23 @@ def test_projected_adam_plan_optimisation_lowers_the_loss(setup):
     assert bool((P >= 0).all()) and abs(float(P.sum()) - total) <= 1e-9 * total
     assert float(c.abs().max()) <= 30.0
     g.close()
+
+
+def test_adjoint_kernel_timing_counts_the_kept_trajectory_launches(setup):
+    from paper_1907_05709_amd import rfa
+    case, ctrl = setup
+    g = rfa.Grid(case.shape, case.spacing, time_kernels=16)
+    g.load_case(case)
+    g.set_perfusion_bspline(ctrl)
+    assert g.adjoint_kernel_stats() == (0.0, 0)
+    P = case.needle.power.copy()
+    _, w = gpu_loss(g, case, P)      # checkpointed: not timed
+    g.adjoint(w.astype(np.float32), len(P), M)
+    assert g.adjoint_kernel_stats() == (0.0, 0)
+    g.reset_state()
+    g.forward_checkpointed(N_STEPS, DT, 0)
+    g.adjoint(w.astype(np.float32), len(P), M)
+    ms, n = g.adjoint_kernel_stats()
+    assert n == N_STEPS and ms > 0.0
+    assert g.adjoint_kernel_stats() == (0.0, 0)
+    g.close()

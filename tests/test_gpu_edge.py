@@ -113,3 +113,28 @@ def test_grids_thinner_than_three_voxels_are_rejected(shape):
     with pytest.raises(rfa.RfaError) as e:
         rfa.Grid(shape, (1e-3, 1e-3, 1e-3))
     assert e.value.status == rfa.RFA_ERR_ARG
+
+
+def test_insulating_vessel_class_exchanges_no_heat():
+    """Eq. (2675-eq6)'s zero-flux reading: a held vessel class with K = 0.
+    Its temperature leaves every free voxel bitwise unchanged on every
+    kernel, and the state matches the oracle."""
+    from helpers import box_case
+    case = box_case(shape=(16, 14, 18), h=0.0, n_steps=60)
+    labels = case.labels.copy()
+    labels[5:9, 4:8, 2:5] = 2
+    wall = dataclasses.replace(case.tissue[0], k=0.0)
+    free = labels == 1
+    for kw in _plans(case.shape):
+        T_free = []
+        for t in (20.0, 80.0):
+            c = dataclasses.replace(case, labels=labels, tissue=[
+                wall, case.tissue[1], W.Tissue(0.0, 1060.0, 3600.0, 0.0, 0.0, t, fixed=1,
+                                               tissue=0)])
+            ost, _, _ = O.run(c)
+            g, T, mask, om, _, _ = parity.gpu_run(c, **kw)
+            parity.compare(c, T, mask, om, ost)
+            assert np.all(T[labels == 2] == t)
+            T_free.append(g.raw_state()[0][free])
+            g.close()
+        assert np.array_equal(T_free[0], T_free[1])

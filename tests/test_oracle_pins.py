@@ -447,3 +447,37 @@ def test_paper_mode_workload_uses_the_printed_constants():
         assert case.spacing[0] * 1e3 == pc["eval_voxel_mm"] and case.dt == pc["eval_dt_s"]
         assert case.dt < O.dt_max(case)
         assert case.tissue[W.LABEL_TIP].t_fixed == tip
+
+
+def test_insulating_class_reading_of_eq6():
+    """Eq. (2675-eq6) read as zero-flux faces toward vessel voxels: a class
+    with K = 0 has zero face conductance (harmonic mean), so a held block of
+    it exchanges no heat.  Its temperature then cannot change any free
+    voxel's trajectory (bitwise), and in a box whose walls are insulating as
+    well, without perfusion, the free voxels gain exactly the injected
+    energy, step by step."""
+    import dataclasses
+    case = box_case(shape=(16, 14, 18), h=0.0, n_steps=60)
+    labels = case.labels.copy()
+    labels[5:9, 4:8, 2:5] = 2                       # a held vessel block
+    wall = dataclasses.replace(case.tissue[0], k=0.0)
+
+    def with_vessel(t):
+        return dataclasses.replace(case, labels=labels, tissue=[
+            wall, case.tissue[1], W.Tissue(0.0, 1060.0, 3600.0, 0.0, 0.0, t, fixed=1,
+                                           tissue=0)])
+
+    c20, c80 = with_vessel(20.0), with_vessel(80.0)
+    q = O.source(c20)
+    s20, _, tr = O.run(c20, q=q, trajectory=True)
+    s80, _, _ = O.run(c80, q=O.source(c80))
+    free = labels == 1
+    assert np.array_equal(s20.T[free], s80.T[free])
+    assert np.all(s20.T[labels == 2] == 20.0) and np.all(s80.T[labels == 2] == 80.0)
+    rc = 1060.0 * 3600.0
+    V = float(np.prod(case.spacing))
+    traj = np.concatenate([tr, s20.T[None]], axis=0)
+    E = (rc * (traj - 37.0) * V * free).sum(axis=(1, 2, 3))
+    inj = float((q * free).sum()) * case.dt * V
+    assert inj > 0
+    assert np.abs(np.diff(E) - inj).max() <= 1e-10 * inj
