@@ -162,40 +162,66 @@ hipError_t launch_adjoint_weight(Grid3 g, const float* w, const float* om, const
   return hipGetLastError();
 }
 
+// The face coefficients of one class pair along one axis, each float-float
+// table entry rounded to float: x = C(q, p) (q's own row), y = C(p, q).
+// Table entries in bytes: row of a class = its masked label << 4, entry =
+// the other class's masked label (the label keeps the class times 8).
+__device__ __forceinline__ float2 pair_from_table(const float2* __restrict__ cf, int axis,
+                                                  unsigned cq, unsigned cp) {
+  const char* t = reinterpret_cast<const char*>(cf + axis * kMaxClasses * kMaxClasses);
+  const float2 a = *reinterpret_cast<const float2*>(t + ((cq << 4) | cp));
+  const float2 b = *reinterpret_cast<const float2*>(t + ((cp << 4) | cq));
+  return make_float2(a.x + a.y, b.x + b.y);
+}
+
+// Pair table: pc[axis][a][c] = pair_from_table(cf, axis, a, c), built once
+// per work-group so the per-voxel update reads one entry per face.
+__device__ __forceinline__ void stage_pairs(float2* pc, float4* cls, const Tables* tab,
+                                            int nthreads) {
+  constexpr int per_axis = kMaxClasses * kMaxClasses;
+  for (int t = threadIdx.x; t < 3 * per_axis; t += nthreads) {
+    const int ax = t / per_axis, r = t - ax * per_axis;
+    const unsigned a = (unsigned)(r / kMaxClasses), c = (unsigned)(r % kMaxClasses);
+    pc[t] = pair_from_table(&tab->cf[0][0], ax, a << kClassShift, c << kClassShift);
+  }
+  if ((int)threadIdx.x < kMaxClasses) cls[threadIdx.x] = tab->cls[threadIdx.x];
+}
+
+// Pair-table lookup in the same byte-offset form.
+__device__ __forceinline__ float2 pair_from_pairs(const float2* __restrict__ pc, int axis,
+                                                  unsigned cq, unsigned cp) {
+  const char* t = reinterpret_cast<const char*>(pc + axis * kMaxClasses * kMaxClasses);
+  return *reinterpret_cast<const float2*>(t + ((cq << 4) | cp));
+}
+
 // Adjoint update of one voxel q: lam_out = (M^T lam_in)_q + w_q dt rate'(theta^n_q),
 // and the accumulations sacc += lam_in_q, facc += lam_in_q (-B theta^n_q), for
 // a free voxel; a held voxel gets lam_out = 0 and accumulates nothing
-// (returns false).  Neighbours in the order x-, x+, y-, y+, z-, z+; cf and
-// cls point at the coefficient tables (global or LDS copy, same layout).
-// Branch-free: a held voxel's neighbour values may be arbitrary (the tiled
-// kernel leaves halo cells outside the grid unwritten) and reach nothing
-// but selects on the held flags.
+// (returns false).  Neighbours in the order x-, x+, y-, y+, z-, z+; pair(axis,
+// cq, cp) gives {C(q, p), C(p, q)} for masked labels, from the forward's
+// tables or from the pair table (the same floats either way); cls points at
+// the class table.  Branch-free: a held voxel's neighbour values may be
+// arbitrary (the tiled kernel leaves halo cells outside the grid unwritten)
+// and reach nothing but selects on the held flags.
+template <class Pair>
 __device__ __forceinline__ bool adjoint_voxel(float lam, float th, unsigned lq, float pf,
                                               float w, const float (&nlam)[6],
-                                              const unsigned (&nlab)[6],
-                                              const float2* __restrict__ cf,
+                                              const unsigned (&nlab)[6], Pair pair,
                                               const float4* __restrict__ cls,
                                               const StepConst& K, float& lam_out,
                                               float& sacc, float& facc) {
   const bool held = (lq & kHeld) != 0u;
   const float4 cl = cls[class_of(lq)];
   const float B = (cl.x + cl.y) * pf;
-  // table entries in bytes: row of a class = its masked label << 4, entry =
-  // the other class's masked label (the label keeps the class times 8)
   const unsigned cq = lq & kClassMask;
-  auto c_at = [&](int axis, unsigned byte_off) {
-    const char* t = reinterpret_cast<const char*>(cf + axis * kMaxClasses * kMaxClasses);
-    const float2 c = *reinterpret_cast<const float2*>(t + byte_off);
-    return c.x + c.y;
-  };
   float diag = 1.0f - B;
   float off = 0.0f;
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     const unsigned lp = nlab[f];
-    const unsigned cp = lp & kClassMask;
-    diag -= c_at(f >> 1, (cq << 4) | cp);                          // C(q, p): q's own row
-    const float o = __builtin_fmaf(c_at(f >> 1, (cp << 4) | cq), nlam[f], off);  // C(p, q)
+    const float2 c = pair(f >> 1, cq, lp & kClassMask);
+    diag -= c.x;                                        // C(q, p): q's own row
+    const float o = __builtin_fmaf(c.y, nlam[f], off);  // C(p, q)
     off = (lp & kHeld) ? off : o;
   }
   // damage-rate derivative at theta^n, the rate evaluated as the forward
@@ -234,8 +260,10 @@ __global__ __launch_bounds__(256) void k_adjoint_step(AdjointBuffers a, StepCons
     nlab[f] = a.lab[nb[f]];
   }
   float lo, sa = a.sacc[q], fa = a.facc[q];
+  const float2* cf = &a.tab->cf[0][0];
   adjoint_voxel(a.lam_in[q], a.theta[q], lq, a.perf ? a.perf[q] : 1.0f, a.w[q], nlam, nlab,
-                &a.tab->cf[0][0], a.tab->cls, K, lo, sa, fa);
+                [cf](int ax, unsigned cq, unsigned cp) { return pair_from_table(cf, ax, cq, cp); },
+                a.tab->cls, K, lo, sa, fa);
   a.lam_out[q] = lo;
   a.sacc[q] = sa;
   a.facc[q] = fa;
@@ -259,7 +287,7 @@ struct AdjSmem {
   static constexpr int W = 66;
   static constexpr int ROWS = TY + 2;
   static constexpr int CELLS = ROWS * W;
-  float2 cf[3 * kMaxClasses * kMaxClasses];
+  float2 pc[3 * kMaxClasses * kMaxClasses];  // pair table
   float4 cls[kMaxClasses];
   float lam[2][CELLS + 1];
   uint8_t lab[2][CELLS + 1];
@@ -283,7 +311,7 @@ __global__ __launch_bounds__(64 * TY) void k_adjoint_tiled(AdjointBuffers a, Ste
   constexpr int W = AdjSmem<TY>::W;
   constexpr int CELLS = AdjSmem<TY>::CELLS;
   __shared__ AdjSmem<TY> sm;
-  stage_tables(sm.cf, sm.cls, a.tab, kMaxClasses, 64 * TY);
+  stage_pairs(sm.pc, sm.cls, a.tab, 64 * TY);
   const int wg = remap_xcd(blockIdx.x, nwg);
   const int tz = wg % tiles_z;
   const int ty = (wg / tiles_z) % tiles_y;
@@ -380,8 +408,11 @@ __global__ __launch_bounds__(64 * TY) void k_adjoint_tiled(AdjointBuffers a, Ste
                               sm.lab[BUF][me - 1], sm.lab[BUF][me + 1]};
     const bool valid = x < x1;  // uniform
     float lo, sa = P.sa, fa = P.fa;
-    const bool free = adjoint_voxel(P.lam, P.th, P.b, P.pf, P.w, nlam, nlab, sm.cf, sm.cls, K,
-                                    lo, sa, fa);
+    const float2* pc = sm.pc;
+    const bool free = adjoint_voxel(
+        P.lam, P.th, P.b, P.pf, P.w, nlam, nlab,
+        [pc](int ax, unsigned cq, unsigned cp) { return pair_from_pairs(pc, ax, cq, cp); },
+        sm.cls, K, lo, sa, fa);
     const int so = (min(x, x1 - 1) - xb) * (int)psz * 4;  // uniform
     const unsigned v = valid ? st4 : kOob;
     st_f32(lo, r_out, v, so);

@@ -116,11 +116,12 @@ def test_adjoint_matches_central_differences(setup):
     g.close()
 
 
-@pytest.mark.parametrize("shape", [(37, 29, 70), (21, 45, 130)])
+@pytest.mark.parametrize("shape", [(37, 29, 70), (21, 45, 130), (19, 23, 67), (9, 40, 258)])
 def test_tiled_adjoint_bitwise_equals_reference(shape):
     """The tiled adjoint kernel (x-march, LDS plane, predicated stores) and
     the one-thread-per-voxel reference share the per-voxel update: the same
-    gradients bit for bit, on ragged tiles with a perfusion field."""
+    gradients bit for bit, on ragged tiles (odd and even nz, a ragged last
+    z tile) with a perfusion field."""
     from paper_1907_05709_amd import rfa
     case = W.random_tissue_case(77, shape=shape, n_classes=5, n_tines=2, n_steps=30)
     field = np.random.default_rng(78).uniform(0.5, 2.0, shape).astype(np.float32)
