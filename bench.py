@@ -40,6 +40,9 @@ BYTES_PER_VOXEL_STEP = 29
 # (4), class (1), weight (4), perfusion factor (4), the two accumulators
 # read + write (8 + 8).
 ADJ_BYTES_PER_VOXEL_STEP = 37
+# Adjoint launch on the 128^3 differentiation grid: 8-row tiles of 64 z, 16 x
+# planes per work-group, 256 work-groups.
+ADJ_PLAN = {"rows": 8, "z": 64, "x_planes": 16, "workgroups": 256}
 HBM_PEAK_GBPS = 8000.0
 # Step-kernel launches per HIP-event-timed block (one event pair per block).
 # A divisor of the library's 64-step diagnostic reduction period keeps those
@@ -55,6 +58,7 @@ KERNEL_SOURCES = {
     "k_step_tiled": ("rfa_tiled.hip", "rfa_tiled.h") + _SHARED,
     "k_step_batch": ("rfa_tiled.hip", "rfa_tiled.h") + _SHARED,
     "k_warp": ("rfa_warp.hip", "rfa_warp.h") + _SHARED,
+    "k_adjoint_tiled": ("rfa_adjoint.hip", "rfa_adjoint.h", "rfa_tiled.h") + _SHARED,
 }
 
 
@@ -363,6 +367,7 @@ def bench_adjoint(args):
         one_step(ckpt)
     torch.cuda.synchronize()
     ck_value = case.n_voxels * n_steps * args.steps / (time.perf_counter() - t1) / 1e9
+    copy_gbps = rfa.rfa_copy_bandwidth(1 << 30, 10)
     g.close()
     value = case.n_voxels * n_steps * args.steps / wall / 1e9
     avg_ms = kms / max(launches, 1)
@@ -377,9 +382,12 @@ def bench_adjoint(args):
            "kernel": kernel_name(plan) + " (forward)", "avg_launch_us": round(avg_ms * 1e3, 3),
            "launches_timed": launches, "bytes_per_launch": bytes_per_launch}
     adj = {"bound": "hbm", "achieved": round(adj_achieved, 1), "peak": HBM_PEAK_GBPS,
-           "unit": "GB/s", "frac": round(adj_achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+           "unit": "GB/s", "frac": round(adj_achieved / HBM_PEAK_GBPS, 4),
+           "traffic": traffic_record(5, ADJ_PLAN, "k_adjoint_tiled",
+                                     "traffic_adjoint_differentiation128.json"),
            "kernel": "k_adjoint_tiled (adjoint)", "avg_launch_us": round(adj_avg_ms * 1e3, 3),
-           "launches_timed": adj_launches, "bytes_per_launch": adj_bytes}
+           "launches_timed": adj_launches, "bytes_per_launch": adj_bytes,
+           "copy_ceiling_GBps": round(copy_gbps, 1)}
     # the dominant kernel (more time in the timed region) carries the roofline
     dominant, other = (adj, fwd) if adj_ms > kms else (fwd, adj)
     out = {
