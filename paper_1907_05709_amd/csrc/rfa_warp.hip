@@ -49,8 +49,11 @@ __device__ __forceinline__ void locate(float s, int i, int n, int& k, float& f) 
   }
 }
 
+// (1 - t) a + t b as two FMAs: exactly a at t = 0 and exactly b at t = 1, so
+// positions on a voxel centre (integer shifts, positions clamped to a wall)
+// return that voxel's value unrounded.
 __device__ __forceinline__ float lerp(float a, float b, float t) {
-  return __builtin_fmaf(t, b - a, a);
+  return __builtin_fmaf(t, b, __builtin_fmaf(-t, a, a));
 }
 
 __global__ __launch_bounds__(kWarpThreads) void k_warp(

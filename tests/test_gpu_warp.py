@@ -91,6 +91,8 @@ def test_displacement_beyond_the_walls_samples_the_walls():
     wall = np.broadcast_to(T[0:1, :, -1:], shape)
     assert np.allclose(ref, wall, rtol=0, atol=1e-9)
     assert np.abs(out - ref).max() <= 2.0 * EPS * (8 * np.abs(T - 37).max() + np.abs(T).max())
+    hi, _ = g.raw_state()     # on the walls the view is the rounded wall voxel, exactly
+    assert np.array_equal(out, np.broadcast_to(np.float32(37.0) + hi[0:1, :, -1:], shape))
     g.close()
 
 
@@ -157,3 +159,32 @@ def test_warp_rejects_bad_arguments():
     with pytest.raises(ValueError):
         g.warp(v[:2], 1.0)
     g.close()
+
+
+def test_integer_shift_is_exact_and_host_equals_device():
+    """With a power-of-two spacing and beta = 1 the shift of k voxels is
+    exact in FP32 and every sample sits on a voxel centre (inside, or
+    clamped to a wall), so the view is the rounded state shifted by k, bit
+    for bit; host and device pointers give the same bits."""
+    import torch
+    shape, d = (12, 10, 33), 2.0 ** -10
+    spacing = (d, d, d)
+    T = W.hot_field(shape, spacing, sigma_m=2e-3, seed=6700)
+    v = np.zeros((3,) + shape, np.float32)
+    v[0] = -2 * d
+    v[2] = 3 * d
+    g = _grid(shape, spacing)
+    g.set_temperature(T)
+    out = g.warp(v, 1.0)
+    hi, _ = g.raw_state()
+    xs = np.clip(np.arange(shape[0]) - 2, 0, shape[0] - 1)
+    zs = np.clip(np.arange(shape[2]) + 3, 0, shape[2] - 1)
+    ref = np.float32(37.0) + hi[xs][:, :, zs]
+    assert np.array_equal(out, ref)
+    assert np.abs(out - warp_oracle(T, v, spacing, 1.0)).max() <= tolerance(T, v, spacing, 1.0)
+    gd = _grid(shape, spacing, device=True)
+    gd.set_temperature(torch.from_numpy(T).cuda())
+    outd = gd.warp(torch.from_numpy(v).cuda(), 1.0).cpu().numpy()
+    assert np.array_equal(outd, out)
+    g.close()
+    gd.close()
