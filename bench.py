@@ -114,6 +114,17 @@ def traffic_record(config: int, plan: dict, kernel: str, name: str = ""):
     return rec.get("hbm_bytes_per_launch")
 
 
+def with_traffic_rate(roofline: dict) -> dict:
+    """Add the measured memory-side rate: the committed below-L2 bytes per
+    launch over the live average launch duration, and its fraction of the
+    peak (null without a valid traffic record)."""
+    t, us = roofline.get("traffic"), roofline.get("avg_launch_us")
+    rate = t / (us * 1e-6) / 1e9 if t and us else None
+    roofline["traffic_GBps"] = round(rate, 1) if rate else None
+    roofline["traffic_frac"] = round(rate / roofline["peak"], 4) if rate else None
+    return roofline
+
+
 def cpu_baseline(case, sample_steps: int):
     """The FP64 oracle (as is) on the host cores: sample_steps steps of the
     same workload, with its per-step diagnostics."""
@@ -221,6 +232,7 @@ def main():
         if steps <= 0:
             steps = max(2, min(case.n_steps, int(2.0e9 / case.n_voxels)))
         out["cpu_baseline"] = cpu_baseline(case, steps)
+    out["roofline"] = with_traffic_rate(out["roofline"])
     print(json.dumps(out), flush=True)
 
 
@@ -308,6 +320,7 @@ def bench_batch(args):
                              "their steps back to back; traffic counts bytes below L2, "
                              "which that cache may serve"},
     }
+    out["roofline"] = with_traffic_rate(out["roofline"])
     print(json.dumps(out), flush=True)
 
 
@@ -410,9 +423,10 @@ def bench_adjoint(args):
                    "checkpointed_every_%d_GVox_s" % ckpt: round(ck_value, 3),
                    "checkpointed_gradients_equal": bool(np.array_equal(dP, dP_ck)),
                    "loss": loss, "dL_dP": [float(x) for x in dP]},
-        "roofline": dominant,
-        "roofline_other_kernel": other,
+        "roofline": with_traffic_rate(dominant),
+        "roofline_other_kernel": with_traffic_rate(other),
     }
+    out["roofline"] = with_traffic_rate(out["roofline"])
     print(json.dumps(out), flush=True)
 
 
@@ -503,6 +517,7 @@ def bench_warp(args):
             "value": n * frames / dt / 1e9, "unit": "GVoxel/s", "cores": 1, "kind": "oracle",
             "sample": f"{frames} full 256^3 frames at spread phases of the cycle, FP64 "
                       f"numpy, {dt:.1f} s wall"}
+    out_json["roofline"] = with_traffic_rate(out_json["roofline"])
     print(json.dumps(out_json), flush=True)
 
 
