@@ -201,6 +201,16 @@ rfa_status rfa_set_temperature(rfa_grid g, const double* t_C);
  * Grids of 2^31 voxels or more give RFA_ERR_ARG. */
 rfa_status rfa_warp(rfa_grid g, const float* v, double beta, float* out, double* kernel_ms);
 
+/* The same view through a displacement combined from two fields,
+ * beta1 v1(x) + beta2 v2(x): the keyframe form of the motion model (two
+ * consecutive phase fields weighted 1 - a and a) or a regression on two
+ * surrogate signals (Sec. "Consideration of Breathing Motion").  v1, v2 as v
+ * above (v2 required); beta1 v1 is rounded to float first and beta2 v2 added
+ * with one fused multiply-add, so beta2 = 0 gives exactly rfa_warp(v1, beta1).
+ * Errors as rfa_warp. */
+rfa_status rfa_warp2(rfa_grid g, const float* v1, double beta1, const float* v2, double beta2,
+                     float* out, double* kernel_ms);
+
 /* Serialise / restore the full dynamic state (temperature, damage, latches,
  * step count) with a checksum.  bytes: in = capacity, out = size needed
  * (call with buf == NULL to query).  A buffer from another grid shape or a

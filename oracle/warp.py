@@ -16,15 +16,22 @@ from __future__ import annotations
 import numpy as np
 
 
-def warp(T: np.ndarray, v: np.ndarray, spacing, beta: float) -> np.ndarray:
+def warp(T: np.ndarray, v: np.ndarray, spacing, beta: float, v2=None,
+         beta2: float = 0.0) -> np.ndarray:
     """T [nx, ny, nz] (degC), v [3, nx, ny, nz] metres, spacing (dx, dy, dz)
-    metres; returns T_ref(x + beta v(x)) at every voxel centre, FP64."""
+    metres; returns T_ref(x + u(x)) at every voxel centre, FP64, with the
+    displacement u = beta v, or u = beta v + beta2 v2 given a second field
+    (the keyframe form of the motion model: two consecutive phase fields
+    weighted 1 - a and a; or a regression on two surrogate signals)."""
     T = np.asarray(T, dtype=np.float64)
     shape = T.shape
     idx = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape], indexing="ij")
     lo, fr = [], []
     for a in range(3):
-        p = idx[a] + float(beta) * np.asarray(v[a], dtype=np.float64) / spacing[a]
+        u = float(beta) * np.asarray(v[a], dtype=np.float64)
+        if v2 is not None:
+            u = u + float(beta2) * np.asarray(v2[a], dtype=np.float64)
+        p = idx[a] + u / spacing[a]
         p = np.clip(p, 0.0, shape[a] - 1.0)
         i0 = np.minimum(np.floor(p), shape[a] - 2).astype(np.int64)
         lo.append(i0)

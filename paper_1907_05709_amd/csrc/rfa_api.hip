@@ -885,38 +885,53 @@ rfa_status rfa_set_temperature(rfa_grid g, const double* t_C) {
   return RFA_OK;
 }
 
-rfa_status rfa_warp(rfa_grid g, const float* v, double beta, float* out, double* kernel_ms) {
+namespace {
+
+// Breathing view with one field (v2 == nullptr) or two.
+rfa_status warp_impl(rfa_grid g, const float* v, double beta, const float* v2, double beta2,
+                     float* out, double* kernel_ms) {
   if (!g || !v || !out) return fail(RFA_ERR_ARG, "grid, v and out are required");
   if (!g->has_tissue) return fail(RFA_ERR_STATE, "no tissue");
-  if (!std::isfinite(beta)) return fail(RFA_ERR_ARG, "beta not finite");
+  if (!std::isfinite(beta) || !std::isfinite(beta2)) return fail(RFA_ERR_ARG, "beta not finite");
   const size_t n = g->g.n();
   if (n >= (size_t(1) << 31)) return fail(RFA_ERR_ARG, "warp needs fewer than 2^31 voxels");
   const bool dev = g->opt.inputs_on_device != 0;
+  const int nf = v2 ? 2 : 1;
   if (!dev) {
-    for (size_t p = 0; p < 3 * n; ++p)
-      if (!std::isfinite(v[p])) return fail(RFA_ERR_ARG, "displacement not finite at %zu", p);
+    for (int f = 0; f < nf; ++f) {
+      const float* w = f ? v2 : v;
+      for (size_t p = 0; p < 3 * n; ++p)
+        if (!std::isfinite(w[p]))
+          return fail(RFA_ERR_ARG, "displacement %d not finite at %zu", f + 1, p);
+    }
   }
-  // beta / spacing in FP64, rounded once: s_a = scale_a * v_a in voxels
-  const float sx = (float)(beta / g->dx), sy = (float)(beta / g->dy), sz = (float)(beta / g->dz);
+  // surrogate / spacing in FP64, rounded once: s_a = scale_a * v_a in voxels
+  const float scale[3] = {(float)(beta / g->dx), (float)(beta / g->dy), (float)(beta / g->dz)};
+  const float scale2[3] = {(float)(beta2 / g->dx), (float)(beta2 / g->dy),
+                           (float)(beta2 / g->dz)};
   float* dv = const_cast<float*>(v);
+  float* dv2 = const_cast<float*>(v2);
   float* dout = out;
   if (!dev) {
-    rfa_status s = dmalloc(&dv, 3 * n);
+    rfa_status s = dmalloc(&dv, (size_t)nf * 3 * n);
     if (s != RFA_OK) return s;
     if ((s = dmalloc(&dout, n)) != RFA_OK) {
       (void)hipFree(dv);
       return s;
     }
+    dv2 = v2 ? dv + 3 * n : nullptr;
   }
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipError_t e = hipSuccess;
   if (!dev) e = hipMemcpyAsync(dv, v, 3 * n * sizeof(float), hipMemcpyHostToDevice, g->st);
+  if (e == hipSuccess && !dev && v2)
+    e = hipMemcpyAsync(dv2, v2, 3 * n * sizeof(float), hipMemcpyHostToDevice, g->st);
   if (e == hipSuccess && kernel_ms) {
     e = hipEventCreate(&ev[0]);
     if (e == hipSuccess) e = hipEventCreate(&ev[1]);
     if (e == hipSuccess) e = hipEventRecord(ev[0], g->st);
   }
-  if (e == hipSuccess) e = launch_warp(g->g, g->hi[g->cur], dv, sx, sy, sz, dout, g->st);
+  if (e == hipSuccess) e = launch_warp(g->g, g->hi[g->cur], dv, scale, dv2, scale2, dout, g->st);
   if (e == hipSuccess && kernel_ms) e = hipEventRecord(ev[1], g->st);
   if (e == hipSuccess && !dev)
     e = hipMemcpyAsync(out, dout, n * sizeof(float), hipMemcpyDeviceToHost, g->st);
@@ -934,6 +949,18 @@ rfa_status rfa_warp(rfa_grid g, const float* v, double beta, float* out, double*
   }
   if (e != hipSuccess) return fail(RFA_ERR_HIP, "warp: %s", hipGetErrorString(e));
   return RFA_OK;
+}
+
+}  // namespace
+
+rfa_status rfa_warp(rfa_grid g, const float* v, double beta, float* out, double* kernel_ms) {
+  return warp_impl(g, v, beta, nullptr, 0.0, out, kernel_ms);
+}
+
+rfa_status rfa_warp2(rfa_grid g, const float* v1, double beta1, const float* v2, double beta2,
+                     float* out, double* kernel_ms) {
+  if (!v2) return fail(RFA_ERR_ARG, "v2 is required");
+  return warp_impl(g, v1, beta1, v2, beta2, out, kernel_ms);
 }
 
 // ---- checkpoint ---------------------------------------------------------------

@@ -26,6 +26,15 @@ namespace {
 constexpr int kWarpThreads = 256;
 constexpr int kVx = 4;
 
+// One displacement field: x, y, z component planes (metres) and the factors
+// that turn them into voxels (surrogate / spacing per axis).
+struct WarpField {
+  const float* x;
+  const float* y;
+  const float* z;
+  float cx, cy, cz;
+};
+
 // Two consecutive floats, 4-byte aligned.
 typedef float pair_f32 __attribute__((ext_vector_type(2), aligned(4)));
 
@@ -56,10 +65,12 @@ __device__ __forceinline__ float lerp(float a, float b, float t) {
   return __builtin_fmaf(t, b, __builtin_fmaf(-t, a, a));
 }
 
-__global__ __launch_bounds__(kWarpThreads) void k_warp(
-    const float* __restrict__ hi, const float* __restrict__ vx, const float* __restrict__ vy,
-    const float* __restrict__ vz, float* __restrict__ out, int nx, int ny, int nz,
-    unsigned n_threads, float cx, float cy, float cz) {
+// Positions s_a = a.c_a * a_a (+ b.c_b * b_a with a second field), in voxels.
+template <bool kTwo>
+__global__ __launch_bounds__(kWarpThreads) void k_warp(const float* __restrict__ hi, WarpField a,
+                                                       WarpField b, float* __restrict__ out,
+                                                       int nx, int ny, int nz,
+                                                       unsigned n_threads) {
   const int wg = tile::remap_xcd(blockIdx.x, gridDim.x);
   const unsigned q = (unsigned)wg * kWarpThreads + threadIdx.x;
   if (q >= n_threads) return;
@@ -75,18 +86,23 @@ __global__ __launch_bounds__(kWarpThreads) void k_warp(
 #pragma unroll
   for (int j = 0; j < kVx; ++j) {
     const unsigned o = (unsigned)min(xg * kVx + j, nx - 1) * sx + yz;
-    ux[j] = vx[o];
-    uy[j] = vy[o];
-    uz[j] = vz[o];
+    ux[j] = a.cx * a.x[o];
+    uy[j] = a.cy * a.y[o];
+    uz[j] = a.cz * a.z[o];
+    if constexpr (kTwo) {
+      ux[j] = __builtin_fmaf(b.cx, b.x[o], ux[j]);
+      uy[j] = __builtin_fmaf(b.cy, b.y[o], uy[j]);
+      uz[j] = __builtin_fmaf(b.cz, b.z[o], uz[j]);
+    }
   }
   float r[kVx];
 #pragma unroll
   for (int j = 0; j < kVx; ++j) {
     int kx, ky, kz;
     float fx, fy, fz;
-    locate(cx * ux[j], min(xg * kVx + j, nx - 1), nx, kx, fx);
-    locate(cy * uy[j], y, ny, ky, fy);
-    locate(cz * uz[j], z, nz, kz, fz);
+    locate(ux[j], min(xg * kVx + j, nx - 1), nx, kx, fx);
+    locate(uy[j], y, ny, ky, fy);
+    locate(uz[j], z, nz, kz, fz);
     const float* p = hi + ((unsigned)kx * sx + (unsigned)ky * sy + (unsigned)kz);
     const pair_f32 c00 = *(const pair_f32*)p;
     const pair_f32 c01 = *(const pair_f32*)(p + sy);
@@ -105,15 +121,22 @@ __global__ __launch_bounds__(kWarpThreads) void k_warp(
 
 }  // namespace
 
-hipError_t launch_warp(Grid3 g, const float* hi, const float* v, float scale_x, float scale_y,
-                       float scale_z, float* out, hipStream_t st) {
+hipError_t launch_warp(Grid3 g, const float* hi, const float* v, const float (&scale)[3],
+                       const float* v2, const float (&scale2)[3], float* out, hipStream_t st) {
   const size_t n = g.n();
   if (n == 0) return hipSuccess;
   if (n >= (size_t(1) << 31) || g.nx < 2 || g.ny < 2 || g.nz < 2) return hipErrorInvalidValue;
   const size_t threads = (size_t)((g.nx + kVx - 1) / kVx) * g.ny * g.nz;
   const unsigned blocks = (unsigned)((threads + kWarpThreads - 1) / kWarpThreads);
-  hipLaunchKernelGGL(k_warp, dim3(blocks), dim3(kWarpThreads), 0, st, hi, v, v + n, v + 2 * n,
-                     out, g.nx, g.ny, g.nz, (unsigned)threads, scale_x, scale_y, scale_z);
+  const WarpField a{v, v + n, v + 2 * n, scale[0], scale[1], scale[2]};
+  if (v2) {
+    const WarpField b{v2, v2 + n, v2 + 2 * n, scale2[0], scale2[1], scale2[2]};
+    hipLaunchKernelGGL(k_warp<true>, dim3(blocks), dim3(kWarpThreads), 0, st, hi, a, b, out,
+                       g.nx, g.ny, g.nz, (unsigned)threads);
+  } else {
+    hipLaunchKernelGGL(k_warp<false>, dim3(blocks), dim3(kWarpThreads), 0, st, hi, a, a, out,
+                       g.nx, g.ny, g.nz, (unsigned)threads);
+  }
   return hipGetLastError();
 }
 

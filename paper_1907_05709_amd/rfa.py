@@ -85,6 +85,8 @@ _SIGS = {
     "rfa_copy_bandwidth": [C.c_size_t, C.c_int, C.POINTER(C.c_double)],
     "rfa_adjoint_kernel_stats": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
     "rfa_warp": [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.POINTER(C.c_double)],
+    "rfa_warp2": [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_double, C.c_void_p,
+                  C.POINTER(C.c_double)],
     "rfa_set_perfusion_bspline": [C.c_void_p, C.c_int, C.c_void_p],
     "rfa_reset_state": [C.c_void_p],
     "rfa_set_tine_powers": [C.c_void_p, C.POINTER(C.c_double)],
@@ -278,6 +280,15 @@ def rfa_warp(g, v_ptr, beta: float, out_ptr, timed: bool = False):
     ms when timed, else None."""
     ms = C.c_double(0.0)
     _check(lib().rfa_warp(g, v_ptr, float(beta), out_ptr, C.byref(ms) if timed else None))
+    return ms.value if timed else None
+
+
+def rfa_warp2(g, v1_ptr, beta1: float, v2_ptr, beta2: float, out_ptr, timed: bool = False):
+    """Breathing view through beta1 v1 + beta2 v2; returns the kernel time
+    in ms when timed, else None."""
+    ms = C.c_double(0.0)
+    _check(lib().rfa_warp2(g, v1_ptr, float(beta1), v2_ptr, float(beta2), out_ptr,
+                           C.byref(ms) if timed else None))
     return ms.value if timed else None
 
 
@@ -515,18 +526,25 @@ class Grid:
             a = np.ascontiguousarray(t, dtype=np.float64)
             rfa_set_temperature(self.h, _ptr(a, False, np.float64))
 
-    def warp(self, v, beta: float, out=None, timed: bool = False):
+    def warp(self, v, beta: float, out=None, timed: bool = False, v2=None, beta2: float = 0.0):
         """Temperature (degC, float) seen through the inverse breathing
-        displacement beta * v, v of shape (3, nx, ny, nz) in metres.  Returns
-        out, or (out, kernel_ms) when timed."""
-        if tuple(v.shape) != (3,) + self.shape:
-            raise ValueError(f"v must have shape {(3,) + self.shape}")
+        displacement beta * v (+ beta2 * v2 with a second field), each of
+        shape (3, nx, ny, nz) in metres.  Returns out, or (out, kernel_ms)
+        when timed."""
+        fields = [v] if v2 is None else [v, v2]
+        for f in fields:
+            if tuple(f.shape) != (3,) + self.shape:
+                raise ValueError(f"displacement fields must have shape {(3,) + self.shape}")
         if out is None:
             out = self._alloc(np.float32)
         if not self.device:
-            v = np.ascontiguousarray(v, dtype=np.float32)
-        ms = rfa_warp(self.h, _ptr(v, self.device, np.float32),
-                      beta, _ptr(out, self.device, np.float32, True), timed)
+            fields = [np.ascontiguousarray(f, dtype=np.float32) for f in fields]
+        ptrs = [_ptr(f, self.device, np.float32) for f in fields]
+        optr = _ptr(out, self.device, np.float32, True)
+        if v2 is None:
+            ms = rfa_warp(self.h, ptrs[0], beta, optr, timed)
+        else:
+            ms = rfa_warp2(self.h, ptrs[0], beta, ptrs[1], beta2, optr, timed)
         return (out, ms) if timed else out
 
     def damage(self):

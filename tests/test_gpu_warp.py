@@ -188,3 +188,62 @@ def test_integer_shift_is_exact_and_host_equals_device():
     assert np.array_equal(outd, out)
     g.close()
     gd.close()
+
+
+def tolerance2(T, v, v2, spacing, beta, beta2):
+    """tolerance() with the position rounding of the two-field sum: the
+    product beta v, one fused multiply-add of beta2 v2, and the two scale
+    roundings, <= 3 eps (|s1| + |s2|) voxels per axis."""
+    theta = np.abs(T - 37.0).max()
+    tol = 8 * theta + np.abs(T).max()
+    for a in range(3):
+        G = np.abs(np.diff(T, axis=a)).max()
+        s = abs(beta) * np.abs(v[a]).max() / spacing[a] + abs(beta2) * np.abs(v2[a]).max() / spacing[a]
+        tol += 3.0 * G * min(s, 2.0 * T.shape[a])
+    return 2.0 * EPS * tol
+
+
+@pytest.mark.parametrize("device", [False, True])
+def test_keyframe_warp_matches_oracle(device):
+    """Two consecutive phase fields blended 1 - a and a (the keyframe form),
+    on a ragged grid, host and device pointers."""
+    import torch
+    shape, spacing = (29, 34, 66), (0.8e-3, 0.7e-3, 0.9e-3)
+    T = W.hot_field(shape, spacing, peak_c=700.0, sigma_m=2.5e-3, seed=6800)
+    v1 = W.breathing_field(shape, spacing, amplitude_m=4e-3, seed=6801)
+    v2 = W.breathing_field(shape, spacing, amplitude_m=6e-3, seed=6802)
+    a = 0.3
+    g = _grid(shape, spacing, device=device)
+    if device:
+        g.set_temperature(torch.from_numpy(T).cuda())
+        out = g.warp(torch.from_numpy(v1).cuda(), 1 - a, v2=torch.from_numpy(v2).cuda(),
+                     beta2=a).cpu().numpy()
+    else:
+        g.set_temperature(T)
+        out = g.warp(v1, 1 - a, v2=v2, beta2=a)
+    ref = warp_oracle(T, v1, spacing, 1 - a, v2, a)
+    err = np.abs(out.astype(np.float64) - ref).max()
+    tol = tolerance2(T, v1, v2, spacing, 1 - a, a)
+    print("keyframe max err", err, "tol", tol)
+    assert err <= tol
+    g.close()
+
+
+def test_second_field_with_zero_weight_is_the_one_field_view():
+    shape, spacing = (17, 21, 40), (1e-3, 1e-3, 1e-3)
+    T = W.hot_field(shape, spacing, seed=6900)
+    v1 = W.breathing_field(shape, spacing, amplitude_m=3e-3, seed=6901)
+    v2 = W.breathing_field(shape, spacing, amplitude_m=5e-3, seed=6902)
+    g = _grid(shape, spacing)
+    g.set_temperature(T)
+    assert np.array_equal(g.warp(v1, 0.8, v2=v2, beta2=0.0), g.warp(v1, 0.8))
+    from paper_1907_05709_amd import rfa
+    bad = v2.copy()
+    bad[2, 3, 4, 5] = np.inf
+    with pytest.raises(rfa.RfaError) as e:
+        g.warp(v1, 0.8, v2=bad, beta2=0.5)
+    assert e.value.status == rfa.RFA_ERR_ARG
+    with pytest.raises(rfa.RfaError) as e:
+        g.warp(v1, 0.8, v2=v2, beta2=float("nan"))
+    assert e.value.status == rfa.RFA_ERR_ARG
+    g.close()

@@ -77,3 +77,22 @@ def test_synthetic_breathing_field_is_smooth_and_bounded():
         assert np.abs(g).max() < 0.6
     assert np.abs(v[:, :, :, 0]).max() == 0.0 and np.abs(v[:, :, :, -1]).max() < 1e-9
     assert W.breathing_surrogate(0.0) == 0.0 and abs(W.breathing_surrogate(2.0) - 1.0) < 1e-12
+
+
+def test_two_fields_match_scipy_and_reduce_to_one():
+    """The two-field displacement beta v + beta2 v2: scipy's order-1
+    interpolation at the clamped combined positions; beta2 = 0 is the
+    one-field view bit for bit; equal fields add their weights."""
+    from scipy.ndimage import map_coordinates
+    T = _T(8)
+    rng = np.random.default_rng(9)
+    v = rng.normal(0.0, 1.5e-3, (3,) + SHAPE)
+    v2 = rng.normal(0.0, 1.5e-3, (3,) + SHAPE)
+    b1, b2 = 0.7, 0.4
+    out = warp(T, v, SPACING, b1, v2, b2)
+    idx = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in SHAPE], indexing="ij")
+    p = np.stack([np.clip(idx[i] + (b1 * v[i] + b2 * v2[i]) / SPACING[i], 0, SHAPE[i] - 1)
+                  for i in range(3)])
+    assert np.abs(out - map_coordinates(T, p, order=1, mode="nearest")).max() < 1e-10
+    assert np.array_equal(warp(T, v, SPACING, b1, v2, 0.0), warp(T, v, SPACING, b1))
+    assert np.abs(warp(T, v, SPACING, b1, v, b2) - warp(T, v, SPACING, b1 + b2)).max() < 1e-10
