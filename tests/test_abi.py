@@ -50,3 +50,20 @@ def test_status_strings_without_gpu():
     assert "stability" in rfa.rfa_status_string(rfa.RFA_ERR_UNSTABLE)
     o = rfa.rfa_default_options()
     assert o.t_death == 60.0 and o.A == 7.39e39 and o.R == 8.314 and o.omega_cap == 1e30
+
+
+@pytest.mark.parametrize("lang,std", [("c", "-std=c99"), ("c++", "-std=c++11")])
+def test_header_compiles_as_plain_c_and_cpp(lang, std, tmp_path):
+    """The boundary is usable from C: the header needs no C++ or HIP types."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc" if lang == "c" else "g++")
+    if cc is None:
+        pytest.skip("no host compiler")
+    src = tmp_path / ("use.c" if lang == "c" else "use.cpp")
+    src.write_text('#include "rfa.h"\nint main(void) { rfa_options o; '
+                   'return rfa_default_options(&o) == RFA_OK ? 0 : 1; }\n')
+    r = subprocess.run([cc, std, "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
+                        "-I", os.path.join(ROOT, "include"), str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
