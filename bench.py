@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune", action="store_true",
                     help="re-tune the launch plan instead of the fixed one")
+    ap.add_argument("--plan", default="",
+                    help="launch plan zv,ty,xc for --config 2/3 instead of the fixed one")
     ap.add_argument("--time-steps", type=int, default=0,
                     help="override the workload's time steps per bench step (profiling runs)")
     args = ap.parse_args()
@@ -176,7 +178,8 @@ def main():
         case.n_steps = args.time_steps
         name += f" [profiling run: {args.time_steps} time steps per bench step]"
     # one step per launch: the HBM-bound kernel whose roofline is reported
-    zv, ty, xc = PLANS[args.config]
+    zv, ty, xc = (tuple(int(t) for t in args.plan.split(",")) if args.plan
+                  else PLANS[args.config])
     g = rfa.Grid(case.shape, case.spacing, device=False, depth=1, z_vec=zv, tile_y=ty,
                  tile_x=xc, time_kernels=TIME_PERIOD)
     g.load_case(case)
