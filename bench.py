@@ -74,7 +74,7 @@ def kernel_hash(kernel: str) -> str:
 # work-group) of the single-grid workloads: the fastest of rfa_tune's
 # candidates on the MI355X, fixed so that the committed counter summaries
 # refer to the timed launch shape.
-PLANS = {2: (2, 8, 4), 3: (4, 4, 32)}
+PLANS = {2: (2, 8, 4), 3: (4, 4, 32), 7: (2, 4, 4)}
 
 
 def kernel_name(plan: dict) -> str:
@@ -95,8 +95,21 @@ def workload(config: int):
         case = W.case_umbrella()
         name = ("9-tine umbrella liver/tumour/vessels 256^3 @0.5mm, 6000 x 0.01 s, "
                 "60 W (seed 3000)")
+    elif config == 7:
+        # the middle y slab [111, 145) of the 256^3 umbrella case: one GPU's
+        # share of eight (32 rows) plus the two halo rows, held here; voxel
+        # centres coincide with the full grid's, the needle's power is
+        # normalised over the slab.  Slabs across y keep the full x extent
+        # for the kernels' x-march (thin x slabs cut it short).
+        import dataclasses
+        import numpy as np
+        full = W.case_umbrella()
+        case = dataclasses.replace(full, shape=(256, 34, 256),
+                                   labels=np.ascontiguousarray(full.labels[:, 111:145]))
+        name = ("y slab 256x34x256 of the 256^3 umbrella case (one GPU's share of 8: 32 rows "
+                "+ 2 halo rows), 6000 x 0.01 s")
     else:
-        raise SystemExit("--config must be 2 or 3")
+        raise SystemExit("--config must be 2, 3, 4, 5, 6 or 7")
     return case, name
 
 
@@ -138,7 +151,7 @@ def cpu_baseline(case, sample_steps: int):
     gvox = case.n_voxels * sample_steps / dt / 1e9
     return {"value": gvox, "unit": "GVoxel-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"first {sample_steps} of {case.n_steps} steps of the same workload "
-                      f"({case.shape[0]}^3), FP64 with per-step diagnostics, "
+                      f"({'x'.join(str(n) for n in case.shape)}), FP64 with per-step diagnostics, "
                       f"{dt:.1f} s wall"}
 
 
