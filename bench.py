@@ -1,6 +1,6 @@
 """Benchmark of the explicit bioheat stepper on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2|3|4|5|6]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2|3|4|5|6|7]
 
 A bench step is one rfa_step call that advances the workload by its full
 simulated duration (all per-step work: conduction, perfusion, RF source,
@@ -10,8 +10,9 @@ workload is the single-instance heterogeneous case: 128^3 voxels at 0.5 mm,
 liver with a tumour and 3-6 vessels, straight needle, 1000 steps of
 0.01 s.  --config 3 runs the 256^3 umbrella-needle case (6000 steps);
 --config 4 the batched sweep, --config 5 the differentiation workload
-(forward + adjoint) and --config 6 the breathing-motion view of a 256^3
-temperature image (one warp per step).
+(forward + adjoint), --config 6 the breathing-motion view of a 256^3
+temperature image (one warp per step) and --config 7 one GPU's share of
+the 256^3 case (its middle y slab, 256x34x256).
 
 Prints one JSON line: voxel-updates/s over the timed steps, the step
 kernel's roofline (algorithmic bytes per launch over its HIP-event-timed

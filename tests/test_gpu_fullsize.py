@@ -46,6 +46,36 @@ def test_umbrella_256_bench_plan_matches_oracle_and_reference():
     ref.close()
 
 
+def test_one_gpu_slab_bench_plan_matches_oracle_and_reference():
+    """The 256x34x256 y slab (one GPU's share of the 256^3 case) in the bench's
+    launch plan: every voxel against the oracle over 300 steps, bitwise
+    against the reference kernel."""
+    import dataclasses
+    from paper_1907_05709_amd import rfa
+    n_steps = 300
+    case, _ = bench.workload(7)
+    case = dataclasses.replace(case, n_steps=n_steps)
+    zv, ty, xc = bench.PLANS[7]
+    g = rfa.Grid(case.shape, case.spacing, depth=1, z_vec=zv, tile_y=ty, tile_x=xc)
+    ref = rfa.Grid(case.shape, case.spacing, kernel=1)
+    for x in (g, ref):
+        x.load_case(case)
+    plan = g.plan()
+    assert (plan["z_vec"], plan["tile_y"], plan["tile_x"]) == (zv, ty, xc)
+    d = g.step(n_steps, case.dt, diag=True)
+    ref.step(n_steps, case.dt, diag=False)
+    T = g.temperature()
+    mask, om, _ = g.damage()
+    for a1, a2 in zip(g.raw_state(), ref.raw_state()):
+        assert np.array_equal(a1, a2)
+    ost, _, _ = O.run(case, n_steps=n_steps)
+    err = parity.compare(case, T, mask, om, ost)
+    print(f"y slab 256x34x256 x {n_steps}: max|dT| = {err:.3e} K, Tmax = {T.max():.2f}")
+    assert d["mono_violations"] == 0
+    g.close()
+    ref.close()
+
+
 def test_planning_sweep_batch_equals_grids_stepped_alone():
     from paper_1907_05709_amd import rfa
     n_steps = 9
