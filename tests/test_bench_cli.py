@@ -41,3 +41,20 @@ def test_committed_traffic_records_name_known_kernels():
             assert names, f
             assert len(bench.kernel_hash(names[0])) == len(rec["kernel_hash"]) == 16
             assert rec["hbm_bytes_per_launch"] > 0 and rec["algorithmic_bytes_per_launch"] > 0
+
+
+def test_one_gpu_slab_is_the_middle_y_slab_of_the_256_case():
+    """The --config 7 workload is rows [111, 145) of the 256^3 umbrella case,
+    with voxel centres (grid-centre frame) identical to the full grid's."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1907_05709_amd import workloads as W
+    slab, _ = bench.workload(7)
+    full = W.case_umbrella()
+    assert slab.shape == (256, 34, 256)
+    assert np.array_equal(slab.labels, full.labels[:, 111:145])
+    ys = W.voxel_axes(slab.shape, slab.spacing)[1]
+    yf = W.voxel_axes(full.shape, full.spacing)[1][111:145]
+    assert np.array_equal(ys, yf)
+    assert np.array_equal(slab.needle.pts, full.needle.pts) and slab.n_steps == full.n_steps
