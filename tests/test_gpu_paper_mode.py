@@ -46,3 +46,26 @@ def test_paper_mode_tip_matches_oracle_and_rises_monotonically(tip_c):
     if tip_c == 90.0:
         assert curves[5.0][5] < 42.5      # 60 s, the paper's statement
     g.close()
+
+
+def test_paper_display_threshold_marks_the_zone():
+    """The 42.5 degC iso-line the paper draws as the ablation-zone border,
+    as the latch threshold: after 60 s with the 90 degC tip the latch mask
+    matches the oracle's, includes the 2.5 mm probe and excludes the 5 mm
+    one."""
+    import dataclasses
+    from paper_1907_05709_amd import rfa
+    case = W.case_paper_mode(tip_c=90.0, n=48, n_steps=600)
+    case = dataclasses.replace(case, t_death=42.5)
+    g = rfa.Grid(case.shape, case.spacing, t_death=case.t_death, A=case.arrhenius_a,
+                 Ea=case.arrhenius_ea, R=case.gas_r, omega_cap=case.omega_cap)
+    g.load_case(case)
+    g.step(case.n_steps, case.dt, diag=True)
+    T = g.temperature()
+    mask, om, _ = g.damage()
+    ost, _, _ = O.run(case)
+    parity.compare(case, T, mask, om, ost)
+    probes = W.paper_probes(case)
+    assert mask[probes[2.5]] & 1 and not mask[probes[5.0]] & 1
+    assert np.array_equal(mask & 1, ost.masks(case) & 1)
+    g.close()
