@@ -51,7 +51,7 @@ class _Problem(C.Structure):
                 ("n_classes", C.c_int), ("q", C.c_void_p), ("perf", C.c_void_p),
                 ("t_blood", C.c_double), ("t_death", C.c_double),
                 ("A", C.c_double), ("Ea", C.c_double), ("R", C.c_double),
-                ("omega_cap", C.c_double)]
+                ("omega_cap", C.c_double), ("perf_decay", C.c_int)]
 
 
 _lib = None
@@ -104,7 +104,7 @@ class Problem:
                           C.cast(tab, C.POINTER(_Tissue)), len(case.tissue),
                           _ptr(self.q), _ptr(self.perf), case.t_blood, case.t_death,
                           case.arrhenius_a, case.arrhenius_ea, case.gas_r,
-                          case.omega_cap)
+                          case.omega_cap, int(getattr(case, "perfusion_decay", False)))
 
     @property
     def ref(self):
@@ -243,6 +243,8 @@ def adjoint(case, w: np.ndarray, n_steps: Optional[int] = None, dt: Optional[flo
     dp = np.zeros(case.shape)
     rc = lib().oracle_adjoint(P.ref, C.c_int(n_steps), C.c_double(dt), _ptr(T0), _ptr(w),
                               _ptr(dq), _ptr(dp))
+    if rc == -2:
+        raise ValueError("no adjoint for damage-coupled perfusion")
     if rc != 0:
         raise MemoryError("oracle_adjoint failed")
     return dq, dp

@@ -37,6 +37,9 @@
  *    line density convolved with an isotropic 3-D Gaussian of width sigma;
  *    the field is zeroed on held voxels and scaled so the tine delivers its
  *    power exactly on the grid.  No truncation.
+ *  - optionally, Linte's tissue-state factor on the perfusion term (Eq.
+ *    (2675-eq1_Linte), Eq. (eq-tissState)): blood cooling scaled by the
+ *    surviving cell fraction exp(-Omega) (perfusion_h);
  *  - discrete adjoint of the stepper (transpose of the linear step, plus the
  *    damage-rate derivative), for gradient checks.
  */
@@ -68,6 +71,8 @@ typedef struct {
   double t_death;              /* necrosis threshold, degC                  */
   double A, Ea, R;             /* Arrhenius: 1/s, J/mol, J/mol/K            */
   double omega_cap;            /* guard on the damage integral              */
+  int perf_decay;              /* 1: perfusion scaled by the surviving cell
+                                  fraction exp(-Omega) (see perfusion_h)    */
 } oracle_problem;
 
 enum { DIAG_ENERGY = 0, DIAG_INJECTED, DIAG_PERFUSION, DIAG_BOUNDARY,
@@ -101,9 +106,20 @@ static double face_k(const oracle_problem* P, int a, int b) {
   return 2.0 * ka * kb / (ka + kb);
 }
 
-static double perfusion_h(const oracle_problem* P, size_t p) {
+/* Perfusion coefficient of voxel p.  With perf_decay, Linte's tissue-state
+ * factor of Eq. (2675-eq1_Linte) scales it: the healthy-cell fraction
+ * c(t)/c(0) = exp(-Omega), since Eq. (eq-tissState) defines the damage
+ * integral as Omega = ln(c(0)/c(t)); it falls from 1 for intact tissue to 0
+ * for dead tissue without blood cooling, as the paper describes the term.
+ * (The printed alpha = 1/ln(c(0)/c(t)) is singular at t = 0, which the
+ * paper points out; the healthy-cell fraction is the reading that has the
+ * stated limits.)  Omega is the voxel's value at the start of the step
+ * (left point, as the damage increment); omega may be NULL (Omega = 0). */
+static double perfusion_h(const oracle_problem* P, size_t p, const double* omega) {
   double h = P->tab[P->labels[p]].h;
-  return P->perf ? h * P->perf[p] : h;
+  if (P->perf) h *= P->perf[p];
+  if (P->perf_decay && omega) h *= exp(-omega[p]);
+  return h;
 }
 
 /* Arrhenius damage rate A exp(-Ea / (R T_K)) with T_K = T + 273.15, capped
@@ -324,7 +340,7 @@ int oracle_run(const oracle_problem* P, int n_steps, double dt, double* T,
           size_t p = vidx(P, i, j, k);
           const oracle_tissue* t = &P->tab[P->labels[p]];
           if (is_free(P, i, j, k)) {
-            double h = perfusion_h(P, p);
+            double h = perfusion_h(P, p, omega);
             double q = P->q ? P->q[p] : 0.0;
             double rhs = conduction(P, cur, i, j, k) + h * (P->t_blood - cur[p]) +
                          t->q_met + q;
@@ -396,7 +412,8 @@ double oracle_dt_max(const oracle_problem* P) {
         if (!is_free(P, i, j, k)) continue;
         size_t p = vidx(P, i, j, k);
         int l = P->labels[p];
-        double s = perfusion_h(P, p);
+        /* the full coefficient bounds the decayed one (exp(-Omega) <= 1) */
+        double s = perfusion_h(P, p, NULL);
         for (int m = 0; m < 6; ++m) {
           size_t nb = vidx(P, i + off[m][0], j + off[m][1], k + off[m][2]);
           s += face_k(P, l, P->labels[nb]) / d2[m / 2];
@@ -421,7 +438,7 @@ void oracle_step_linear(const oracle_problem* P, double dt, const double* x, dou
         size_t p = vidx(P, i, j, k);
         if (!is_free(P, i, j, k)) { y[p] = x[p]; continue; }
         const oracle_tissue* t = &P->tab[P->labels[p]];
-        double rhs = conduction(P, x, i, j, k) - perfusion_h(P, p) * x[p];
+        double rhs = conduction(P, x, i, j, k) - perfusion_h(P, p, NULL) * x[p];
         y[p] = x[p] + dt / (t->rho * t->c) * rhs;
       }
 }
@@ -445,7 +462,7 @@ void oracle_step_linear_transpose(const oracle_problem* P, double dt, const doub
         double v;
         int qfree = is_free(P, i, j, k);
         if (qfree) {
-          double diag = perfusion_h(P, q);
+          double diag = perfusion_h(P, q, NULL);
           for (int m = 0; m < 6; ++m) {
             size_t nb = vidx(P, i + off[m][0], j + off[m][1], k + off[m][2]);
             diag += face_k(P, lq, P->labels[nb]) / d2[m / 2];
@@ -479,6 +496,9 @@ void oracle_step_linear_transpose(const oracle_problem* P, double dt, const doub
  */
 int oracle_adjoint(const oracle_problem* P, int n_steps, double dt, const double* T0,
                    const double* w, double* dq, double* dperf) {
+  /* the damage-coupled perfusion makes the step nonlinear in (T, Omega);
+   * its adjoint is not part of this oracle */
+  if (P->perf_decay) return -2;
   size_t n = (size_t)P->nx * P->ny * P->nz;
   double* traj = (double*)malloc((size_t)n_steps * n * sizeof(double));
   double* T = (double*)malloc(n * sizeof(double));

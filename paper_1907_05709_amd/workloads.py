@@ -104,6 +104,10 @@ class Case:
     gas_r: float = GAS_R
     omega_cap: float = OMEGA_CAP
     t_blood: float = T_BLOOD
+    # perfusion scaled by the surviving cell fraction exp(-Omega) (Linte's
+    # tissue-state factor; off in the planning workloads, as in the paper's
+    # own model)
+    perfusion_decay: bool = False
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -380,6 +384,20 @@ def case_umbrella(n: int = 256, dx: float = 0.5e-3, dt: float = 0.01,
                 dt, n_steps, seed,
                 meta=dict(tumour_centre=tumour_c.tolist(), tumour_radius=tumour_r,
                           vessels=vessels, direction=direction.tolist()))
+
+
+def case_umbrella_window(n: int = 160, **kw) -> Case:
+    """The centred n^3 window of the umbrella workload: the same needle,
+    time step and step count and the same tissue labels on the window's
+    voxels (voxel centres coincide with the full grid's, since both grids
+    are centred), with the window's outer layer held at 37 degC."""
+    full = case_umbrella(**kw)
+    o = (full.shape[0] - n) // 2
+    if o < 0 or (full.shape[0] - n) % 2:
+        raise ValueError("the window must be centred inside the full grid")
+    labels = _with_boundary(np.ascontiguousarray(full.labels[o:o + n, o:o + n, o:o + n]))
+    return dataclasses.replace(full, name=f"umbrella_window{n}", shape=(n, n, n),
+                               labels=labels)
 
 
 def case_planning_instance(instance: int, n_min: int = 64, n_max: int = 160,

@@ -481,3 +481,226 @@ def test_insulating_class_reading_of_eq6():
     inj = float((q * free).sum()) * case.dt * V
     assert inj > 0
     assert np.abs(np.diff(E) - inj).max() <= 1e-10 * inj
+
+
+# --------------------------------------------------------------------------
+# M': the per-step count of cooling voxels, fixed by geometry.  The explicit
+# update of a free voxel is (1 - a) T + sum_nb c_nb T_nb + sources with all
+# coefficients positive below dt_max, so from a state that is uniform apart
+# from one region, the set of voxels whose temperature changes in step s is
+# exactly the set within s face-steps of that region, and the sign of the
+# change follows from the sign of the region's offset.
+# --------------------------------------------------------------------------
+def _l1_distance_to_block(shape, lo, hi):
+    """Manhattan distance of every voxel to the box [lo, hi) (0 inside)."""
+    ax = []
+    for n, a, b in zip(shape, lo, hi):
+        i = np.arange(n)
+        ax.append(np.maximum(a - i, 0) + np.maximum(i - (b - 1), 0))
+    return ax[0][:, None, None] + ax[1][None, :, None] + ax[2][None, None, :]
+
+
+@pytest.mark.parametrize("h", [0.0, 24306.24])
+def test_cooling_count_of_a_hot_cube(h):
+    """A hot n^3 cube in a 37 degC box without source.  Without perfusion
+    only its surface voxels cool in the first step (interior voxels see no
+    gradient and stay put, the neighbours outside warm up); with perfusion
+    every cube voxel cools.  A counter stuck at 0, counting <= instead of <,
+    or counting held voxels fails one of the two."""
+    case = box_case((16, 15, 17), (1e-3,) * 3, h=h, dt=0.05)
+    lo, hi = (5, 4, 6), (10, 9, 11)                # a 5^3 cube
+    T0, om, tm = O.initial_state(case)
+    T0 = T0.copy()
+    T0[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] = 70.0
+    _, dg, _ = O.run(case, n_steps=1, q=np.zeros(case.shape), state=O.State(T0, om, tm),
+                     diag=True)
+    n = 5
+    expect = n ** 3 if h > 0 else n ** 3 - (n - 2) ** 3
+    assert dg[0, 5] == expect, (dg[0, 5], expect)
+
+
+def test_cooling_count_next_to_a_held_cold_block():
+    """Free voxels at 60 degC (walls held at 60 degC, no perfusion, no
+    source) around a held block at 20 degC: in step s exactly the free
+    voxels within Manhattan distance s of the block cool (the diffusion
+    front moves one voxel per step), every other voxel keeps its value."""
+    shape = (22, 21, 23)
+    case = box_case(shape, (0.8e-3, 1e-3, 1.1e-3), h=0.0, dt=0.04, t_boundary=60.0)
+    lo, hi = (9, 8, 10), (12, 13, 12)              # 3 x 5 x 2 held block
+    case.tissue.append(W.Tissue(case.tissue[1].k, 1060.0, 3600.0, 0.0, 0.0, 20.0,
+                                fixed=1, tissue=0))
+    case.labels[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] = 2
+    assert case.dt < O.dt_max(case)
+    free = _free_mask(case)
+    T0, om, tm = O.initial_state(case)
+    T0 = np.where(free, 60.0, T0)
+    steps = 6
+    _, dg, tr = O.run(case, n_steps=steps, q=np.zeros(case.shape),
+                      state=O.State(T0, om, tm), diag=True, trajectory=True)
+    dist = _l1_distance_to_block(shape, lo, hi)
+    for s in range(steps):
+        expect = int(((dist >= 1) & (dist <= s + 1) & free).sum())
+        assert dg[s, 5] == expect, (s, dg[s, 5], expect)
+    # the geometric count for the first step is the block's face area
+    a, b, c = (h_ - l_ for h_, l_ in zip(hi, lo))
+    assert dg[0, 5] == 2 * (a * b + b * c + c * a)
+
+
+# --------------------------------------------------------------------------
+# dt_max: the positivity bound rho c / (sum_faces K_f / d^2 + h) in closed
+# form, and the maximum principle on both sides of it
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("spacing,h", [((1e-3, 1e-3, 1e-3), 24306.24),
+                                       ((0.5e-3, 0.8e-3, 0.6e-3), 189892.5),
+                                       ((0.7e-3, 0.7e-3, 0.7e-3), 0.0)])
+def test_dt_max_closed_form_homogeneous(spacing, h):
+    K, rho, c = 0.52, 1060.0, 3600.0
+    case = box_case((9, 10, 11), spacing, k=K, rho=rho, c=c, h=h)
+    inv = sum(1.0 / d ** 2 for d in spacing)
+    expect = rho * c / (2.0 * K * inv + h)
+    assert math.isclose(O.dt_max(case), expect, rel_tol=1e-14), (O.dt_max(case), expect)
+
+
+def test_dt_max_of_a_single_conductive_voxel():
+    """One free voxel of a second class (K_b) in a liver box: its faces
+    carry the harmonic mean 2 K_a K_b / (K_a + K_b); the bound is the
+    smaller of that voxel's and the plain liver voxels'."""
+    Ka, Kb, rho, c, h = 0.52, 5.0, 1060.0, 3600.0, 24306.24
+    d = 0.5e-3
+    case = box_case((9, 9, 9), (d, d, d), k=Ka, h=h)
+    case.tissue.append(W.Tissue(Kb, 900.0, 2000.0, 0.0, 0.0))
+    case.labels[4, 4, 4] = 2
+    kf = 2 * Ka * Kb / (Ka + Kb)
+    own = 900.0 * 2000.0 / (6 * kf / d ** 2)
+    liver_next = rho * c / ((5 * Ka + kf) / d ** 2 + h)   # liver voxel beside it
+    expect = min(own, liver_next, rho * c / (6 * Ka / d ** 2 + h))
+    assert math.isclose(O.dt_max(case), expect, rel_tol=1e-14)
+
+
+def test_maximum_principle_holds_below_and_fails_just_above_dt_max():
+    """A checkerboard start between 40 and 80 degC without sources or
+    perfusion (walls held at 60 degC): at 0.999 dt_max every voxel stays in
+    [40, 80]; at 1.001 dt_max the diagonal coefficient of the update is
+    negative and a voxel leaves that range in the first step."""
+    case = box_case((12, 11, 13), (0.6e-3, 0.9e-3, 0.7e-3), h=0.0, t_boundary=60.0)
+    dtm = O.dt_max(case)
+    i, j, k = np.indices(case.shape)
+    T0, om, tm = O.initial_state(case)
+    T0 = np.where(_free_mask(case), np.where((i + j + k) % 2 == 0, 80.0, 40.0), T0)
+    for f, inside in ((0.999, True), (1.001, False)):
+        st, _, _ = O.run(case, n_steps=1, dt=f * dtm, q=np.zeros(case.shape),
+                         state=O.State(T0, om, tm))
+        ok = st.T.min() >= 40.0 - 1e-12 and st.T.max() <= 80.0 + 1e-12
+        assert ok == inside, (f, st.T.min(), st.T.max())
+
+
+# --------------------------------------------------------------------------
+# Damage-coupled perfusion (Linte's tissue-state factor, Eq. (2675-eq1_Linte)
+# with Eq. (eq-tissState)): blood cooling scaled by the surviving cell
+# fraction exp(-Omega), Omega taken at the start of the step
+# --------------------------------------------------------------------------
+def _decay_box(h, A, n_steps, dt, shape=(9, 10, 11), theta0=40.0, k=0.0):
+    """Insulated box (K = 0 walls) of free voxels at 37 + theta0 degC in a
+    checkerboard of a tissue class and a non-tissue class (same parameters),
+    no source, Q_m = 0, damage rate A at every temperature (Ea = 0)."""
+    import dataclasses
+    case = box_case(shape, (1e-3,) * 3, k=k, h=h, dt=dt, n_steps=n_steps)
+    wall = dataclasses.replace(case.tissue[0], k=0.0)
+    other = dataclasses.replace(case.tissue[1], tissue=0)
+    i, j, kk = np.indices(shape)
+    labels = case.labels.copy()
+    labels[(labels == 1) & ((i + j + kk) % 2 == 1)] = 2
+    case = dataclasses.replace(case, labels=labels, tissue=[wall, case.tissue[1], other],
+                               arrhenius_a=A, arrhenius_ea=0.0, perfusion_decay=True)
+    T0, om, tm = O.initial_state(case)
+    T0 = np.where(labels > 0, 37.0 + theta0, T0)
+    T0[0], T0[-1] = 37.0, 37.0
+    T0[:, 0], T0[:, -1] = 37.0, 37.0
+    T0[:, :, 0], T0[:, :, -1] = 37.0, 37.0
+    return case, O.State(T0, om, tm)
+
+
+def test_decayed_perfusion_uniform_closed_form():
+    """With Ea = 0 the damage integral grows as Omega^n = n dt A whatever the
+    temperature, so an insulated uniform voxel without conduction follows
+    theta^n = theta0 prod_{m<n} (1 - b exp(-m dt A)), b = dt h / (rho c),
+    while a non-tissue voxel (no damage) keeps the full perfusion,
+    theta0 (1 - b)^n."""
+    h, A, dt, n = 24306.24, 0.3, 0.05, 400
+    case, st0 = _decay_box(h, A, n, dt)
+    st, _, _ = O.run(case, q=np.zeros(case.shape), state=st0)
+    b = dt * h / (1060.0 * 3600.0)
+    m = np.arange(n)
+    tis = 40.0 * np.prod(1.0 - b * np.exp(-m * dt * A))
+    non = 40.0 * (1.0 - b) ** n
+    free = _free_mask(case)
+    assert np.allclose(st.T[free & (case.labels == 1)] - 37.0, tis, rtol=1e-12, atol=0)
+    assert np.allclose(st.T[free & (case.labels == 2)] - 37.0, non, rtol=1e-12, atol=0)
+    assert np.allclose(st.omega[case.labels == 1], n * dt * A, rtol=1e-12)
+    assert tis > non + 3.0                     # decayed cooling leaves the tissue warmer
+
+
+def test_decayed_perfusion_continuum_limit():
+    """The time-continuous uniform problem d theta/dt = -(h/rho c) e^(-A t)
+    theta integrates to theta0 exp(-(h / (rho c A)) (1 - e^(-A t))): the
+    discrete scheme converges to it at first order in dt."""
+    h, A, t_end = 24306.24, 0.5, 6.0
+    rc = 1060.0 * 3600.0
+    exact = 40.0 * math.exp(-(h / (rc * A)) * (1.0 - math.exp(-A * t_end)))
+    errs = []
+    for dt in (0.02, 0.01):
+        n = int(round(t_end / dt))
+        case, st0 = _decay_box(h, A, n, dt, shape=(5, 5, 5))
+        st, _, _ = O.run(case, q=np.zeros(case.shape), state=st0)
+        errs.append(abs(st.T[2, 2, 2] - 37.0 - exact) / exact)
+    assert errs[0] < 2e-3, errs
+    assert 1.8 < errs[0] / errs[1] < 2.2, errs
+
+
+def test_decayed_perfusion_without_damage_is_the_plain_scheme():
+    """A = 0: Omega stays 0, the factor is exp(0) = 1 and the coupled scheme
+    is the plain one bit for bit (heterogeneous case with a needle)."""
+    import dataclasses
+    case = W.random_tissue_case(17, shape=(14, 13, 15), n_steps=60)
+    plain = dataclasses.replace(case, arrhenius_a=0.0)
+    coupled = dataclasses.replace(plain, perfusion_decay=True)
+    q = O.source(case)
+    s1, _, _ = O.run(plain, q=q)
+    s2, _, _ = O.run(coupled, q=q)
+    assert np.array_equal(s1.T, s2.T)
+    s3, _, _ = O.run(dataclasses.replace(case, perfusion_decay=True), q=q)
+    assert not np.array_equal(s1.T, s3.T)      # with damage the coupling acts
+
+
+def test_decayed_perfusion_switches_off_after_instant_death():
+    """A damage rate so large (Ea = 0, A = 1e6 1/s) that Omega = dt A after
+    the first step: that step still cools with the full perfusion (Omega at
+    its start is 0); from the second step exp(-Omega) = 0 and the homogeneous
+    box follows the DST-I closed form of the perfusion-free scheme started
+    from the first step's state."""
+    import dataclasses
+    shape, spacing, dt = (20, 18, 16), (1e-3,) * 3, 0.05
+    base = box_case(shape, spacing, h=24306.24, dt=dt,
+                    needle=W.straight_needle([0.3e-3, -0.2e-3, 2e-3], [0.2, 0.1, 1.0],
+                                             5e-3, 12.0, 1e-3))
+    case = dataclasses.replace(base, arrhenius_a=1e6, arrhenius_ea=0.0,
+                               perfusion_decay=True)
+    q = O.source(case)
+    s1, _, _ = O.run(case, n_steps=1, q=q)
+    ref1, _, _ = O.run(dataclasses.replace(base, arrhenius_a=1e6, arrhenius_ea=0.0),
+                       n_steps=1, q=q)
+    assert np.array_equal(s1.T, ref1.T)       # first step: full perfusion
+    n = 200
+    st, _, _ = O.run(case, n_steps=n, q=q, state=s1)
+    t = case.tissue[1]
+    ref = analytic.dst_solution(interior(s1.T) - 37.0, interior(q), t.k, t.rho, t.c, 0.0,
+                                spacing, dt, n)
+    assert np.abs(interior(st.T) - 37.0 - ref).max() <= 1e-10
+
+
+def test_decayed_perfusion_has_no_oracle_adjoint():
+    import dataclasses
+    case = dataclasses.replace(W.random_tissue_case(18, shape=(8, 8, 8), n_steps=4),
+                               perfusion_decay=True)
+    with pytest.raises(ValueError):
+        O.adjoint(case, np.zeros(case.shape))
