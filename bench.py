@@ -1,23 +1,30 @@
 """Benchmark of the explicit bioheat stepper on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2|3|4|5|6|7]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4|2|3|5|6|7]
 
-A bench step is one rfa_step call that advances the workload by its full
-simulated duration (all per-step work: conduction, perfusion, RF source,
-held voxels, float-float Euler update, Arrhenius damage and latch,
-per-step diagnostics), with the grid's inputs resident in HBM.  The default
-workload is the single-instance heterogeneous case: 128^3 voxels at 0.5 mm,
-liver with a tumour and 3-6 vessels, straight needle, 1000 steps of
-0.01 s.  --config 3 runs the 256^3 umbrella-needle case (6000 steps);
---config 4 the batched sweep, --config 5 the differentiation workload
-(forward + adjoint), --config 6 the breathing-motion view of a 256^3
-temperature image (one warp per step) and --config 7 one GPU's share of
-the 256^3 case (its middle y slab, 256x34x256).
+The default workload (--config 4) is the batched planning sweep: 64 grids of
+64^3..160^3 voxels at 0.5..1 mm, each with its own tissue, needle (straight,
+3-tine or 9-tine umbrella), power and time step, 2000 steps each.  A bench
+step is one rfa_batch_step call that advances every grid by its 2000 steps
+(all per-step work: conduction, perfusion, RF source, held voxels,
+float-float Euler update, Arrhenius damage and latch, per-step
+diagnostics), with every input resident in HBM.  The plain stepper (each
+grid stepped on its own, one after another) is timed beside it.  The
+default line also carries two legs, each with its own roofline and CPU
+baseline: the 256^3 umbrella-needle case (6000 steps, one grid) and the
+differentiation workload (128^3, 600 steps, forward + adjoint with a
+checkpoint every 50 steps).  --no-legs leaves them out.
 
-Prints one JSON line: voxel-updates/s over the timed steps, the step
+Single workloads: --config 2 the 128^3 straight-needle case (1000 steps;
+its state stays in the 256 MB last-level cache), 3 the 256^3 umbrella
+case, 5 the differentiation workload, 6 the breathing-motion view of a
+256^3 temperature image (one cycle of 100 warps per step) and 7 one GPU's
+share of the 256^3 case (its middle y slab, 256x34x256).
+
+Prints one JSON line: voxel-updates/s over the timed steps, the dominant
 kernel's roofline (algorithmic bytes per launch over its HIP-event-timed
-average duration), and the FP64 oracle timed on this host's cores on a
-bounded sample of the same workload.
+average duration), and the FP64 oracle timed on this host's cores (all of
+them, and one) on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -139,21 +146,117 @@ def with_traffic_rate(roofline: dict) -> dict:
     return roofline
 
 
-def cpu_baseline(case, sample_steps: int):
-    """The FP64 oracle (as is) on the host cores: sample_steps steps of the
-    same workload, with its per-step diagnostics."""
+def _threads() -> int:
+    return int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(cases, steps_all: int, steps_one: int, what: str):
+    """The FP64 oracle (as is, with its per-step diagnostics) on the host
+    cores: steps_all steps of every case in `cases` with all cores, then
+    steps_one steps with one core.  The RF sources are computed first and
+    not timed (setup)."""
     from oracle import oracle as O
     O.build(force=False)
-    q = O.source(case)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    qs = [O.source(c) for c in cases]
+    vox = sum(c.n_voxels for c in cases)
+    threads = _threads()
+    out = {}
+    for n_thr, steps in ((threads, steps_all), (1, steps_one)):
+        O.set_threads(n_thr)
+        t0 = time.perf_counter()
+        for c, q in zip(cases, qs):
+            O.run(c, n_steps=steps, q=q, diag=True)
+        dt = time.perf_counter() - t0
+        out[n_thr == 1] = (vox * steps / dt / 1e9, dt)
+    O.set_threads(threads)
+    (v_all, t_all), (v_one, t_one) = out[False], out[True]
+    return {"value": round(v_all, 4), "unit": "GVoxel-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{what}: first {steps_all} steps with {threads} threads ({t_all:.1f} s "
+                      f"wall), {steps_one} steps with 1 thread ({t_one:.1f} s); FP64 with "
+                      f"per-step diagnostics; sources computed beforehand, untimed",
+            "single_core": {"value": round(v_one, 5), "unit": "GVoxel-updates/s", "cores": 1}}
+
+
+def roofline_dict(bytes_per_launch, avg_ms, kernel, **extra):
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": kernel,
+         "avg_launch_us": round(avg_ms * 1e3, 3), "bytes_per_launch": round(bytes_per_launch)}
+    r.update(extra)
+    return r
+
+
+def run_single(config: int, steps: int, warmup: int, plan_arg: str = "", tune: bool = False,
+               time_steps: int = 0, cpu: bool = True, cpu_steps: int = 0) -> dict:
+    """One grid stepped by its whole duration per bench step (configs 2, 3,
+    7); returns the result fields of its JSON line."""
+    import torch
+    from paper_1907_05709_amd import rfa
+    case, name = workload(config)
+    if time_steps > 0:
+        case.n_steps = time_steps
+        name += f" [profiling run: {time_steps} time steps per bench step]"
+    # one step per launch: the HBM-bound kernel whose roofline is reported
+    zv, ty, xc = (tuple(int(t) for t in plan_arg.split(",")) if plan_arg else PLANS[config])
+    g = rfa.Grid(case.shape, case.spacing, device=False, depth=1, z_vec=zv, tile_y=ty,
+                 tile_x=xc, time_kernels=TIME_PERIOD)
+    g.load_case(case)
+    if tune:
+        g.tune(case.dt, reps=10)
+    plan = g.plan()
+    for _ in range(warmup):
+        g.step(case.n_steps, case.dt, diag=True)
+    g.kernel_stats()  # reset
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    O.run(case, n_steps=sample_steps, q=q, diag=True)
-    dt = time.perf_counter() - t0
-    gvox = case.n_voxels * sample_steps / dt / 1e9
-    return {"value": gvox, "unit": "GVoxel-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {sample_steps} of {case.n_steps} steps of the same workload "
-                      f"({'x'.join(str(n) for n in case.shape)}), FP64 with per-step diagnostics, "
-                      f"{dt:.1f} s wall"}
+    diag = None
+    for _ in range(steps):
+        diag = g.step(case.n_steps, case.dt, diag=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, launches, _ = g.kernel_stats()
+    copy_gbps = rfa.rfa_copy_bandwidth(1 << 30, 10)
+    g.close()
+
+    value = case.n_voxels * case.n_steps * steps / wall / 1e9
+    avg_ms = kms / launches
+    roof = roofline_dict(BYTES_PER_VOXEL_STEP * case.n_voxels, avg_ms, kernel_name(plan),
+                         launches_timed=launches, copy_ceiling_GBps=round(copy_gbps, 1))
+    roof["traffic"] = traffic_record(config, plan, kernel_name(plan))
+    # working set of one step: state in and out, class, source, damage
+    ws_mb = case.n_voxels * (16 + 1 + 4 + 4) / 1e6
+    if ws_mb < 200.0:
+        roof["note"] = (f"the {ws_mb:.0f} MB working set stays in the 256 MB last-level "
+                        f"cache: the launch is latency bound and 'hbm' names the peak it is "
+                        f"priced against, not the level that serves it")
+        roof["cache_resident"] = True
+    out = {
+        "value": round(value, 3),
+        "unit": "GVoxel-updates/s",
+        "ms_per_step": round(wall / steps * 1e3, 4),
+        "config": {"workload": name, "grid": list(case.shape), "time_steps": case.n_steps,
+                   "dt_s": case.dt, "state": "float-float f32 excess temperature",
+                   "plan": plan},
+        "roofline": with_traffic_rate(roof),
+        "diag_last_step": {k: diag[k] for k in ("t_max_C", "mono_violations", "residual_J")},
+    }
+    if cpu:
+        n = cpu_steps or max(2, min(case.n_steps, int(2.0e9 / case.n_voxels)))
+        out["cpu_baseline"] = cpu_baseline([case], n, max(1, n // 25),
+                                           f"the same workload ({'x'.join(map(str, case.shape))})")
+    return out
+
+
+def line(fields: dict, steps: int, warmup: int) -> dict:
+    out = {"metric": METRIC, "value": fields["value"], "unit": fields["unit"], "n_gpus": 1,
+           "steps": steps, "warmup": warmup, "ms_per_step": fields["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic"}
+    for k, v in fields.items():
+        if k not in out:
+            out[k] = v
+    return out
 
 
 def main():
@@ -161,10 +264,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--cpu-steps", type=int, default=0,
                     help="oracle sample steps (0 = size for ~15 s)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="--config 4: leave out the 256^3 and differentiation legs")
     ap.add_argument("--tune", action="store_true",
                     help="re-tune the launch plan instead of the fixed one")
     ap.add_argument("--plan", default="",
@@ -173,87 +278,44 @@ def main():
                     help="override the workload's time steps per bench step (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
+                                   "(the build targets a single MI355X)"}))
         sys.exit(2)
 
     import torch
-    from paper_1907_05709_amd import rfa
+    from paper_1907_05709_amd import rfa  # noqa: F401  (fails loudly if not built)
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.config == 4:
-        return bench_batch(args)
+        out = line(bench_batch(args), args.steps, args.warmup)
+        if not args.no_legs:
+            out["legs"] = {
+                "umbrella256": run_single(3, steps=2, warmup=1, cpu=not args.no_cpu,
+                                          cpu_steps=60),
+                "differentiation128": bench_adjoint(args, steps=3, warmup=1),
+            }
+        print(json.dumps(out), flush=True)
+        return
     if args.config == 5:
-        return bench_adjoint(args)
+        print(json.dumps(line(bench_adjoint(args, args.steps, args.warmup), args.steps,
+                              args.warmup)), flush=True)
+        return
     if args.config == 6:
         return bench_warp(args)
-    case, name = workload(args.config)
-    if args.time_steps > 0:
-        case.n_steps = args.time_steps
-        name += f" [profiling run: {args.time_steps} time steps per bench step]"
-    # one step per launch: the HBM-bound kernel whose roofline is reported
-    zv, ty, xc = (tuple(int(t) for t in args.plan.split(",")) if args.plan
-                  else PLANS[args.config])
-    g = rfa.Grid(case.shape, case.spacing, device=False, depth=1, z_vec=zv, tile_y=ty,
-                 tile_x=xc, time_kernels=TIME_PERIOD)
-    g.load_case(case)
-    if args.tune:
-        g.tune(case.dt, reps=10)
-    plan = g.plan()
-    for _ in range(args.warmup):
-        g.step(case.n_steps, case.dt, diag=True)
-    g.kernel_stats()  # reset
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    diag = None
-    for _ in range(args.steps):
-        diag = g.step(case.n_steps, case.dt, diag=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kms, launches, vsteps = g.kernel_stats()
-    copy_gbps = rfa.rfa_copy_bandwidth(1 << 30, 10)
-    g.close()
-
-    vox_updates = case.n_voxels * case.n_steps * args.steps
-    value = vox_updates / wall / 1e9
-    avg_ms = kms / launches
-    bytes_per_launch = BYTES_PER_VOXEL_STEP * case.n_voxels
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = traffic_record(args.config, plan, kernel_name(plan))
-    out = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "GVoxel-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": name, "grid": list(case.shape), "time_steps": case.n_steps,
-                   "dt_s": case.dt, "state": "float-float f32 excess temperature",
-                   "plan": plan},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic, "kernel": kernel_name(plan),
-                     "avg_launch_us": round(avg_ms * 1e3, 3),
-                     "launches_timed": launches, "bytes_per_launch": bytes_per_launch,
-                     "copy_ceiling_GBps": round(copy_gbps, 1)},
-        "diag_last_step": {k: diag[k] for k in ("t_max_C", "mono_violations", "residual_J")},
-    }
-    if not args.no_cpu:
-        steps = args.cpu_steps
-        if steps <= 0:
-            steps = max(2, min(case.n_steps, int(2.0e9 / case.n_voxels)))
-        out["cpu_baseline"] = cpu_baseline(case, steps)
-    out["roofline"] = with_traffic_rate(out["roofline"])
-    print(json.dumps(out), flush=True)
+    if args.config not in (2, 3, 7):
+        raise SystemExit("--config must be 2, 3, 4, 5, 6 or 7")
+    fields = run_single(args.config, args.steps, args.warmup, args.plan, args.tune,
+                        args.time_steps, cpu=not args.no_cpu, cpu_steps=args.cpu_steps)
+    print(json.dumps(line(fields, args.steps, args.warmup)), flush=True)
 
 
-def bench_batch(args):
+# Planning-sweep instances timed by the oracle for the CPU baseline (one in
+# eight, all three needle types and the size range) and their steps.
+SWEEP_CPU_SAMPLE = tuple(range(0, 64, 8))
+
+
+def bench_batch(args) -> dict:
     """Planning sweep: 64 uneven grids (64^3..160^3, 0.5..1 mm, own needle,
     dt = 0.01 s (dx / 0.5 mm)^2), 2000 steps each; one bench step is one
     batched call advancing every grid by its 2000 steps (grids grouped to
@@ -305,52 +367,50 @@ def bench_batch(args):
     launches = plan["groups"] * n_steps * args.steps
     avg_launch_ms = dev_ms / launches
     bytes_per_launch = BYTES_PER_VOXEL_STEP * total_vox / plan["groups"]
-    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    copy_gbps = rfa.rfa_copy_bandwidth(1 << 30, 10)
     b.close()
     for g in grids:
         g.close()
+    roof = roofline_dict(bytes_per_launch, avg_launch_ms, "k_step_batch",
+                         launches_timed=launches, copy_ceiling_GBps=round(copy_gbps, 1),
+                         note="groups of grids sized to the 256 MB last-level cache run "
+                              "their steps back to back; traffic counts bytes below L2, "
+                              "which that cache may serve")
+    roof["traffic"] = traffic_record(4, plan, "k_step_batch")
     out = {
-        "metric": METRIC,
         "value": round(value, 3),
         "unit": "GVoxel-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": round(wall / args.steps * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
         "config": {"workload": f"planning sweep: 64 grids 64^3..160^3 @0.5..1 mm, straight / "
                                f"3-tine / 9-tine needles, {n_steps} steps each, per-grid dt "
                                f"(seeds 4000..4063)",
                    "voxels": total_vox, "time_steps": n_steps, "batch_plan": plan,
+                   "state": "float-float f32 excess temperature",
                    "plain_stepper_GVox_s": round(seq_value, 3),
                    "batched_speedup_vs_plain": round(value / seq_value, 3)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic_record(4, plan, "k_step_batch"), "kernel": "k_step_batch",
-                     "avg_launch_us": round(avg_launch_ms * 1e3, 3),
-                     "bytes_per_launch": round(bytes_per_launch),
-                     "note": "groups of grids sized to the 256 MB last-level cache run "
-                             "their steps back to back; traffic counts bytes below L2, "
-                             "which that cache may serve"},
+        "roofline": with_traffic_rate(roof),
     }
-    out["roofline"] = with_traffic_rate(out["roofline"])
-    print(json.dumps(out), flush=True)
+    if not args.no_cpu:
+        sample = [cases[i] for i in SWEEP_CPU_SAMPLE]
+        steps_all = args.cpu_steps or 100
+        out["cpu_baseline"] = cpu_baseline(
+            sample, steps_all, max(1, steps_all // 25),
+            f"sweep instances {', '.join(map(str, SWEEP_CPU_SAMPLE))} "
+            f"({sum(c.n_voxels for c in sample)} voxels) of the same sweep")
+    return out
 
 
-def bench_adjoint(args):
+def bench_adjoint(args, steps: int, warmup: int) -> dict:
     """Differentiation workload: 128^3 at 0.5 mm, 9-tine umbrella (60 W
     shared by length), 600 steps of 0.02 s, perfusion corrected by a 16^3
-    B-spline lattice (all zero).  One bench step = reset, forward keeping the
-    temperature of every step in HBM (5 GB), coverage loss and its gradient
-    with respect to the damage integral (torch, on the GPU), adjoint to the 9
-    tine powers and the 4096 lattice values.  value = simulated voxel-steps
-    per second of forward + adjoint.  The checkpointed schedule (state every
-    50 steps, each segment recomputed in the adjoint; same gradients, bitwise)
-    is timed beside it."""
+    B-spline lattice (all zero).  One bench step = reset, forward with a
+    checkpoint every 50 steps, coverage loss and its gradient with respect
+    to the damage integral (torch, on the GPU), adjoint (each 50-step
+    segment recomputed from its checkpoint) to the 9 tine powers and the
+    4096 lattice values.  value = simulated voxel-steps per second of
+    forward + adjoint.  The schedule that keeps every step's temperature in
+    HBM (5 GB, no recomputation; same gradients, bitwise) is timed beside
+    it, and its launches give the kernels' rooflines."""
     import numpy as np
     import torch
     from paper_1907_05709_amd import rfa
@@ -367,7 +427,7 @@ def bench_adjoint(args):
     labels = torch.from_numpy(case.labels).cuda()
     vox = float(np.prod(case.spacing))
 
-    def one_step(every=0):
+    def one_step(every):
         g.reset_state()
         g.forward_checkpointed(n_steps, case.dt, every)
         _, om, _ = g.damage()
@@ -377,77 +437,95 @@ def bench_adjoint(args):
         dP, dc, _ = g.adjoint(w.float(), case.needle.n_tines, m)
         return float(loss.detach()), dP
 
-    for _ in range(args.warmup):
-        one_step()
+    def timed(every):
+        for _ in range(warmup):
+            one_step(every)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            loss, dP = one_step(every)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, loss, dP
+
+    wall, loss, dP = timed(ckpt)
+    value = case.n_voxels * n_steps * steps / wall / 1e9
+    # kept trajectory: value beside it, and the kernels' launch timing
     g.kernel_stats()
     g.adjoint_kernel_stats()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        loss, dP = one_step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    kwall, _, dP_kept = timed(0)
+    kept_value = case.n_voxels * n_steps * steps / kwall / 1e9
     kms, launches, _ = g.kernel_stats()
     adj_ms, adj_launches = g.adjoint_kernel_stats()
-    # the checkpointed schedule, for comparison (not part of value)
-    _, dP_ck = one_step(ckpt)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        one_step(ckpt)
-    torch.cuda.synchronize()
-    ck_value = case.n_voxels * n_steps * args.steps / (time.perf_counter() - t1) / 1e9
     copy_gbps = rfa.rfa_copy_bandwidth(1 << 30, 10)
     g.close()
-    value = case.n_voxels * n_steps * args.steps / wall / 1e9
     avg_ms = kms / max(launches, 1)
-    # the perfusion factor field adds one float read per voxel-step
-    bytes_per_launch = (BYTES_PER_VOXEL_STEP + 4) * case.n_voxels
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     adj_avg_ms = adj_ms / max(adj_launches, 1)
-    adj_bytes = ADJ_BYTES_PER_VOXEL_STEP * case.n_voxels
-    adj_achieved = adj_bytes / (adj_avg_ms * 1e-3) / 1e9
-    fwd = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-           "kernel": kernel_name(plan) + " (forward)", "avg_launch_us": round(avg_ms * 1e3, 3),
-           "launches_timed": launches, "bytes_per_launch": bytes_per_launch}
-    adj = {"bound": "hbm", "achieved": round(adj_achieved, 1), "peak": HBM_PEAK_GBPS,
-           "unit": "GB/s", "frac": round(adj_achieved / HBM_PEAK_GBPS, 4),
-           "traffic": traffic_record(5, ADJ_PLAN, "k_adjoint_tiled",
-                                     "traffic_adjoint_differentiation128.json"),
-           "kernel": "k_adjoint_tiled (adjoint)", "avg_launch_us": round(adj_avg_ms * 1e3, 3),
-           "launches_timed": adj_launches, "bytes_per_launch": adj_bytes,
-           "copy_ceiling_GBps": round(copy_gbps, 1)}
+    # the perfusion factor field adds one float read per voxel-step
+    fwd = roofline_dict((BYTES_PER_VOXEL_STEP + 4) * case.n_voxels, avg_ms,
+                        kernel_name(plan) + " (forward)", launches_timed=launches)
+    adj = roofline_dict(ADJ_BYTES_PER_VOXEL_STEP * case.n_voxels, adj_avg_ms,
+                        "k_adjoint_tiled (adjoint)", launches_timed=adj_launches,
+                        copy_ceiling_GBps=round(copy_gbps, 1))
+    adj["traffic"] = traffic_record(5, ADJ_PLAN, "k_adjoint_tiled",
+                                    "traffic_adjoint_differentiation128.json")
     # the dominant kernel (more time in the timed region) carries the roofline
     dominant, other = (adj, fwd) if adj_ms > kms else (fwd, adj)
     out = {
-        "metric": METRIC,
         "value": round(value, 3),
         "unit": "GVoxel-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
+        "ms_per_step": round(wall / steps * 1e3, 3),
         "config": {"workload": f"differentiation: 9-tine umbrella 128^3 @0.5mm, {n_steps} x "
                                f"{case.dt} s, 16^3 B-spline perfusion lattice; value counts "
-                               f"forward + adjoint per simulated step",
-                   "trajectory": "every step's temperature kept in HBM, no recomputation",
-                   "checkpointed_every_%d_GVox_s" % ckpt: round(ck_value, 3),
-                   "checkpointed_gradients_equal": bool(np.array_equal(dP, dP_ck)),
-                   "loss": loss, "dL_dP": [float(x) for x in dP]},
+                               f"forward + adjoint per simulated step, checkpoint every "
+                               f"{ckpt} steps with recomputation",
+                   "kept_trajectory_GVox_s": round(kept_value, 3),
+                   "kept_trajectory_gradients_equal": bool(np.array_equal(dP, dP_kept)),
+                   "loss": loss, "dL_dP": [float(x) for x in dP],
+                   "rooflines_from": "the kept-trajectory launches (same kernels and "
+                                     "launch shapes; the checkpointed schedule adds the "
+                                     "recompute steps)"},
         "roofline": with_traffic_rate(dominant),
         "roofline_other_kernel": with_traffic_rate(other),
     }
-    out["roofline"] = with_traffic_rate(out["roofline"])
-    print(json.dumps(out), flush=True)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_adjoint()
+    return out
 
 
-WARP_BYTES_PER_VOXEL = 20   # displacement (3 x 4) + source image (4) + output (4)
+def cpu_baseline_adjoint() -> dict:
+    """The oracle's discrete adjoint (its forward, keeping the trajectory,
+    then the FP64 transpose of every step with the damage-rate derivative)
+    on the differentiation workload's 32^3 copy, all host cores and one; the
+    rate counts forward + adjoint per simulated voxel-step, as the GPU's
+    value does.  The weights dL/dOmega are seeded random numbers (the cost
+    does not depend on them)."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1907_05709_amd import workloads as W
+    O.build(force=False)
+    case = W.case_differentiation(n=32, dx=2e-3, n_steps=600)
+    q, gt, _ = O.source(case, per_tine=True)
+    f = O.bspline_field(case.shape, np.zeros((16, 16, 16)))
+    w = np.random.default_rng(5).standard_normal(case.shape) * 1e-3
+    threads = _threads()
+    res = {}
+    for n_thr in (threads, 1):
+        O.set_threads(n_thr)
+        t0 = time.perf_counter()
+        O.adjoint(case, w, q=q, perf=f)     # forward (trajectory kept), then the adjoint
+        res[n_thr == 1] = time.perf_counter() - t0
+    O.set_threads(threads)
+    vs = case.n_voxels * case.n_steps
+    return {"value": round(vs / res[False] / 1e9, 5), "unit": "GVoxel-updates/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"the workload's 32^3 copy at 2 mm, 600 x 0.02 s: forward + discrete "
+                      f"adjoint, FP64 ({res[False]:.1f} s with {threads} threads, "
+                      f"{res[True]:.1f} s with 1)",
+            "single_core": {"value": round(vs / res[True] / 1e9, 5),
+                            "unit": "GVoxel-updates/s", "cores": 1}}
+
+
+WARP_BYTES_PER_VOXEL = 24   # displacement (3 x 4) + float-float state (8) + output (4)
 WARP_PLAN = {"threads": 256, "x_voxels_per_thread": 4}
 WARP_FRAMES_PER_CYCLE = 100
 
@@ -494,7 +572,7 @@ def bench_warp(args):
     launches = args.steps * len(betas)
     avg_ms = e0.elapsed_time(e1) / launches
     # keyframe form, for comparison (not part of value): two phase fields
-    # blended over the cycle, 32 algorithmic bytes per voxel
+    # blended over the cycle, 36 algorithmic bytes per voxel
     v2 = torch.from_numpy(W.breathing_field(shape, spacing, amplitude_m=12e-3, seed=7001)).cuda()
     for b in betas[:10]:
         g.warp(v, 1.0 - b, out=out, v2=v2, beta2=b)
@@ -528,7 +606,7 @@ def bench_warp(args):
                                "trilinear; one step = one 4 s breathing cycle, 100 frames",
                    "keyframe_two_fields": {"avg_launch_us": round(kf_ms * 1e3, 3),
                                            "GVox_s": round(n / (kf_ms * 1e-3) / 1e9, 1),
-                                           "algorithmic_GBps": round(32 * n / (kf_ms * 1e-3) / 1e9, 1)}},
+                                           "algorithmic_GBps": round(36 * n / (kf_ms * 1e-3) / 1e9, 1)}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic_record(6, WARP_PLAN, "k_warp",

@@ -99,8 +99,8 @@ typedef struct {
 /* Grid options; rfa_default_options fills the defaults given per field. */
 typedef struct {
   double t_death;     /* necrosis latch threshold, degC (60)                */
-  double A;           /* Arrhenius frequency factor, 1/s (7.39e39)          */
-  double Ea;          /* activation energy, J/mol (2.577e5)                 */
+  double A;           /* Arrhenius frequency factor, 1/s, >= 0 (7.39e39)    */
+  double Ea;          /* activation energy, J/mol, >= 0 (2.577e5)           */
   double R;           /* gas constant, J/mol/K (8.314)                      */
   double omega_cap;   /* cap of the damage integral (1e30)                  */
   void* stream;       /* hipStream_t for all device work (NULL)            */
@@ -108,8 +108,9 @@ typedef struct {
   int depth;          /* steps per kernel launch: 1, or 2 = temporal
                          blocking (tiled kernel, tile_y 8 or 16; two steps
                          per pass over memory, bitwise equal to two single
-                         steps; odd step counts end with a single step);
-                         0 = automatic (0)                                   */
+                         steps; odd step counts end with a single step;
+                         one step per launch while damage-coupled perfusion
+                         is on); 0 = automatic (0)                           */
   int kernel;         /* 0 automatic, 1 reference one-thread-per-voxel,
                          2 tiled 2.5-D (0)                                   */
   int tile_y;         /* tiled kernel: y rows per work-group (4, 8, 16);
@@ -135,15 +136,23 @@ typedef struct {
   double perfusion_J;     /* heat removed by perfusion during the call       */
   double boundary_J;      /* heat received from held voxels during the call  */
   double residual_J;      /* energy change - (injected - perfusion + boundary)*/
-  long long mono_violations; /* sum over steps of free voxels that cooled    */
+  long long mono_violations; /* sum over steps of free voxels that cooled by
+                                more than 2^-18 |T - 37 degC| in a step (the
+                                check of the monotone rise of Sec. "Results";
+                                smaller falls are FP32 rounding near balance) */
   double t_min_C, t_max_C;   /* temperature range after the call            */
   long long steps;           /* steps taken by the call                      */
 } rfa_diag;
 
 rfa_status rfa_default_options(rfa_options* opt);
 
-/* Create an nx x ny x nz grid (each >= 3) with spacing dx, dy, dz metres.
- * opt may be NULL (defaults).  The grid has no tissue until rfa_set_tissue. */
+/* Create an nx x ny x nz grid (each >= 3) with spacing dx, dy, dz metres:
+ * the voxel image on which Eq. (CUDAbioheat3d) is discretised, its spacing
+ * the voxel distances of that equation (taken in metres; the text's
+ * millimetres would be inconsistent with K in W/m/K).  Voxel (i, j, k) sits
+ * at [i][j][k], k fastest.  opt may be NULL (defaults).  The grid owns its
+ * device memory until rfa_destroy_grid; RFA_ERR_OOM if it does not fit.  The
+ * grid has no tissue until rfa_set_tissue. */
 rfa_status rfa_create_grid(int nx, int ny, int nz, double dx, double dy, double dz,
                            const rfa_options* opt, rfa_grid* out);
 
@@ -164,6 +173,18 @@ rfa_status rfa_set_needle(rfa_grid g, const rfa_needle* needle);
  * f >= 0, [nx*ny*nz] float; NULL removes it (f = 1). */
 rfa_status rfa_set_perfusion(rfa_grid g, const float* factor);
 
+/* Damage-coupled perfusion (enable = 1; 0 turns it off, the default): the
+ * blood-cooling term of the free voxels is scaled by the surviving cell
+ * fraction c(t)/c(0) = exp(-Omega), Linte's tissue-state factor of Eq.
+ * (2675-eq1_Linte) read through Eq. (eq-tissState), which defines the damage
+ * integral as Omega = ln(c(0)/c(t)); Omega is the voxel's value at the start
+ * of each step.  Dead tissue then loses its blood cooling.  Without a
+ * perfusion field the grid gets one of ones.  The dt bound is that of the
+ * uncoupled grid (exp(-Omega) <= 1).  While it is on, rfa_adjoint returns
+ * RFA_ERR_ARG (the step is no longer linear in the temperature alone).
+ * RFA_ERR_STATE before rfa_set_tissue; RFA_ERR_ARG for other values. */
+rfa_status rfa_set_perfusion_decay(rfa_grid g, int enable);
+
 /* Advance n_steps explicit steps of length dt seconds (Eq. (CUDAbioheat3d),
  * Alg. 1 and 2).  dt above the bound min over free voxels of
  * rho c / (sum_faces K_face / d^2 + h) gives RFA_ERR_UNSTABLE.  diag may be
@@ -173,14 +194,21 @@ rfa_status rfa_step(rfa_grid g, int n_steps, double dt, rfa_diag* diag);
 /* Largest dt accepted by rfa_step for the current tissue and perfusion. */
 rfa_status rfa_dt_max(rfa_grid g, double* dt_max);
 
-/* Damage outputs (any may be NULL): mask bit0 = latched T >= t_death,
- * bit1 = damage integral >= 1 (tissue classes only); omega = damage
- * integral (float); dead_m3[2*n_classes] = per class dead volume by bit0
- * then by bit1, m^3. */
+/* Damage outputs (any may be NULL): mask bit0 = latched T >= t_death (the
+ * Introduction's instant cell death above 60 degC, threshold t_death), bit1 =
+ * damage integral >= 1 (Eq. (eq-tissState), Arrhenius with T in Kelvin;
+ * tissue classes only); omega = damage integral (float); dead_m3[2*n_classes]
+ * = per class dead volume by bit0 then by bit1, m^3 (the ablation zone of
+ * Sec. "Results").  mask [nx*ny*nz] u8 and omega [nx*ny*nz] are caller
+ * owned, host or device per inputs_on_device; dead_m3 is host memory.  Host
+ * outputs synchronise the grid's stream. */
 rfa_status rfa_damage(rfa_grid g, uint8_t* mask, float* omega, double* dead_m3);
 
-/* Temperature outputs (any may be NULL): t_C = 37 + hi + lo summed in FP64,
- * degC; hi, lo = the raw float-float excess-temperature state. */
+/* Temperature outputs (any may be NULL): the current temperature image, the
+ * per-frame output of Alg. 1 and 2 (Sec. "Implementation").  t_C = 37 + hi +
+ * lo summed in FP64, degC, [nx*ny*nz] double; hi, lo = the raw float-float
+ * excess-temperature state, [nx*ny*nz] float each.  Caller-owned buffers,
+ * host or device per inputs_on_device; host outputs synchronise. */
 rfa_status rfa_get_temperature(rfa_grid g, double* t_C, float* hi, float* lo);
 
 /* Overwrite the temperature state (degC, double, [nx*ny*nz]); damage and
@@ -189,8 +217,9 @@ rfa_status rfa_set_temperature(rfa_grid g, const double* t_C);
 
 /* Breathing-motion view of the current temperature (Eq. (eq:breathing)):
  * out[x] = T(x + beta v(x)) in degC, T taken trilinearly between voxel
- * centres from the float excess-temperature state (the hi word), sample
- * positions beyond the grid taken on its walls.  v: [3][nx*ny*nz] float, the
+ * centres from the float-float temperature state (sample positions in FP64,
+ * the interpolant rounded once to float: within 1e-4 K of the exact
+ * interpolant), sample positions beyond the grid taken on its walls.  v: [3][nx*ny*nz] float, the
  * x, y and z components of the inverse breathing displacement in metres;
  * beta: the breathing surrogate (finite); out: [nx*ny*nz] float, caller
  * owned.  v and out are host or device pointers per inputs_on_device; on
@@ -205,8 +234,9 @@ rfa_status rfa_warp(rfa_grid g, const float* v, double beta, float* out, double*
  * beta1 v1(x) + beta2 v2(x): the keyframe form of the motion model (two
  * consecutive phase fields weighted 1 - a and a) or a regression on two
  * surrogate signals (Sec. "Consideration of Breathing Motion").  v1, v2 as v
- * above (v2 required); beta1 v1 is rounded to float first and beta2 v2 added
- * with one fused multiply-add, so beta2 = 0 gives exactly rfa_warp(v1, beta1).
+ * above (v2 required); the position beta1 v1 + beta2 v2 is one FP64 fused
+ * multiply-add on top of beta1 v1, so beta2 = 0 gives exactly
+ * rfa_warp(v1, beta1).
  * Errors as rfa_warp. */
 rfa_status rfa_warp2(rfa_grid g, const float* v1, double beta1, const float* v2, double beta2,
                      float* out, double* kernel_ms);

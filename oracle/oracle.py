@@ -266,3 +266,9 @@ def bspline_grad(f: np.ndarray, gf: np.ndarray, m: int) -> np.ndarray:
     lib().oracle_bspline_grad(C.c_int(f.shape[0]), C.c_int(f.shape[1]), C.c_int(f.shape[2]),
                               C.c_int(m), _ptr(f), _ptr(gf), _ptr(g))
     return g
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's parallel loops (the benchmark's
+    single-core timing)."""
+    lib().omp_set_num_threads(C.c_int(int(n)))

@@ -78,6 +78,7 @@ struct rfa_grid_s {
   float* src = nullptr;
   double* q64 = nullptr;
   float* perf = nullptr;  // null = no perfusion multiplier
+  bool perf_decay = false;  // perfusion scaled by exp(-Omega); needs perf (ones if unset)
   Tables* tab_dev = nullptr;
   Tables tab_host{};
   double tab_dt = -1.0;
@@ -241,7 +242,20 @@ StepConst step_const(rfa_grid g, double dt) {
   K.clamp2 = (float)(kExponentClamp * M_LOG2E);
   K.cap = (float)g->opt.omega_cap;
   K.thr = (float)(g->opt.t_death - 37.0);
+  K.decay2 = g->perf_decay ? (float)M_LOG2E : 0.0f;
   return K;
+}
+
+// A perfusion field of ones (allocated if missing), for damage-coupled
+// perfusion without a multiplier of its own.
+rfa_status unit_perf(rfa_grid g) {
+  if (!g->perf) {
+    rfa_status s = dmalloc(&g->perf, g->g.n());
+    if (s != RFA_OK) return s;
+  }
+  HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)g->perf, 0x3f800000, g->g.n(), g->st));
+  HIP_TRY(hipStreamSynchronize(g->st));
+  return RFA_OK;
 }
 
 rfa_status compute_dt_max(rfa_grid g) {
@@ -425,7 +439,11 @@ rfa_status timed_steps(rfa_grid g, const StepConst& K, int n_steps, bool diag,
                        float* traj = nullptr, int* traj_t = nullptr) {
   StepState ss{g->hi, g->lo, &g->cur, g->lab, g->src, g->om, g->perf, g->tab_dev,
                g->n_classes};
-  const StepPlan plan = traj ? plan_one(g->plan) : g->plan;
+  // one step per launch for the kept trajectory, and with damage-coupled
+  // perfusion: the two-step kernel reads the damage integral of its halo
+  // voxels while the neighbouring work-groups overwrite it, harmless while
+  // the damage integral feeds no temperature
+  const StepPlan plan = (traj || g->perf_decay) ? plan_one(g->plan) : g->plan;
   if (traj) {
     ss.traj = traj;
     ss.traj_t = traj_t;
@@ -548,7 +566,8 @@ rfa_status rfa_create_grid(int nx, int ny, int nz, double dx, double dy, double 
   } else {
     rfa_default_options(&o);
   }
-  if (!std::isfinite(o.t_death) || !(o.A >= 0.0) || !std::isfinite(o.A) || !finite_pos(o.Ea) ||
+  if (!std::isfinite(o.t_death) || !(o.A >= 0.0) || !std::isfinite(o.A) || !(o.Ea >= 0.0) ||
+      !std::isfinite(o.Ea) ||
       !finite_pos(o.R) || !finite_pos(o.omega_cap) || o.omega_cap > 3.0e38)
     return fail(RFA_ERR_ARG, "invalid damage options");
   if (o.depth < 0 || o.depth > kMaxDepth) return fail(RFA_ERR_ARG, "depth must be 0, 1 or 2");
@@ -738,6 +757,11 @@ rfa_status rfa_set_perfusion(rfa_grid g, const float* factor) {
   ++g->version;
   g->bs_m = 0;  // a plain multiplier replaces any B-spline field
   if (!factor) {
+    if (g->perf_decay) {
+      rfa_status s = unit_perf(g);
+      if (s != RFA_OK) return s;
+      return compute_dt_max(g);
+    }
     if (g->perf) (void)hipFree(g->perf);
     g->perf = nullptr;
     return compute_dt_max(g);
@@ -753,6 +777,20 @@ rfa_status rfa_set_perfusion(rfa_grid g, const float* factor) {
   }
   HIP_TRY(hipMemcpyAsync(g->perf, factor, n * sizeof(float), kind_in(g), g->st));
   return compute_dt_max(g);
+}
+
+rfa_status rfa_set_perfusion_decay(rfa_grid g, int enable) {
+  if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "set_tissue before set_perfusion_decay");
+  if (enable != 0 && enable != 1) return fail(RFA_ERR_ARG, "enable must be 0 or 1");
+  if (enable && !g->perf) {
+    // the coupling is applied by the kernels that read a perfusion field
+    rfa_status s = unit_perf(g);
+    if (s != RFA_OK) return s;
+  }
+  if ((bool)enable != g->perf_decay) ++g->version;
+  g->perf_decay = enable != 0;
+  return RFA_OK;
 }
 
 rfa_status rfa_dt_max(rfa_grid g, double* dt_max) {
@@ -905,10 +943,9 @@ rfa_status warp_impl(rfa_grid g, const float* v, double beta, const float* v2, d
           return fail(RFA_ERR_ARG, "displacement %d not finite at %zu", f + 1, p);
     }
   }
-  // surrogate / spacing in FP64, rounded once: s_a = scale_a * v_a in voxels
-  const float scale[3] = {(float)(beta / g->dx), (float)(beta / g->dy), (float)(beta / g->dz)};
-  const float scale2[3] = {(float)(beta2 / g->dx), (float)(beta2 / g->dy),
-                           (float)(beta2 / g->dz)};
+  // surrogate / spacing (FP64): s_a = scale_a * v_a in voxels
+  const double scale[3] = {beta / g->dx, beta / g->dy, beta / g->dz};
+  const double scale2[3] = {beta2 / g->dx, beta2 / g->dy, beta2 / g->dz};
   float* dv = const_cast<float*>(v);
   float* dv2 = const_cast<float*>(v2);
   float* dout = out;
@@ -931,7 +968,8 @@ rfa_status warp_impl(rfa_grid g, const float* v, double beta, const float* v2, d
     if (e == hipSuccess) e = hipEventCreate(&ev[1]);
     if (e == hipSuccess) e = hipEventRecord(ev[0], g->st);
   }
-  if (e == hipSuccess) e = launch_warp(g->g, g->hi[g->cur], dv, scale, dv2, scale2, dout, g->st);
+  if (e == hipSuccess)
+    e = launch_warp(g->g, g->hi[g->cur], g->lo[g->cur], dv, scale, dv2, scale2, dout, g->st);
   if (e == hipSuccess && kernel_ms) e = hipEventRecord(ev[1], g->st);
   if (e == hipSuccess && !dev)
     e = hipMemcpyAsync(out, dout, n * sizeof(float), hipMemcpyDeviceToHost, g->st);
@@ -1386,6 +1424,9 @@ rfa_status rfa_forward_checkpointed(rfa_grid g, int n_steps, double dt, int ckpt
 rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* dL_dctrl,
                        float* dL_dperf) {
   if (!g || !w_omega) return fail(RFA_ERR_ARG, "grid and w_omega are required");
+  if (g->perf_decay)
+    return fail(RFA_ERR_ARG, "no adjoint for damage-coupled perfusion (the step is then "
+                             "nonlinear in the damage integral)");
   if (!g->adj_ready || g->version != g->adj_version)
     return fail(RFA_ERR_STATE, "no checkpointed forward for the current state");
   if (dL_dctrl && !g->bs_m) return fail(RFA_ERR_STATE, "no B-spline perfusion field");
@@ -1412,6 +1453,9 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
   HIP_TRY(hipMemcpyAsync(wv, w_omega, n * sizeof(float), kind_in(g), g->st));
   HIP_TRY(launch_adjoint_weight(g->g, wv, g->om, g->lab, (float)g->opt.omega_cap, wv, g->st));
   HIP_TRY(hipMemsetAsync(g->adj_work + 2 * n, 0, 4 * n * sizeof(float), g->st));
+  // the recompute's damage integral is never read back, but the step kernels
+  // take it as an input: keep it finite
+  HIP_TRY(hipMemsetAsync(om_s, 0, n * sizeof(float), g->st));
   HIP_TRY(hipMemcpyAsync(g->lab_scratch, g->lab, n, hipMemcpyDeviceToDevice, g->st));
   if ((s = prepare_dt(g, g->adj_dt)) != RFA_OK) return s;
   const StepConst K = step_const(g, g->adj_dt);

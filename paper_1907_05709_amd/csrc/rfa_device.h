@@ -11,11 +11,14 @@
 // Voxel update (Eq. (CUDAbioheat3d) with per-class conductivity in flux form,
 // Alg. 1 for held voxels), in excess temperature:
 //   theta' = theta + sum_axes [C(l,l-)(theta- - theta) + C(l,l+)(theta+ - theta)]
-//                  - B_l f_p theta + Qs_l + s_p
+//                  - B_l f_p g_p theta + Qs_l + s_p
 // with C(a,b) = dt K_face(a,b) / (rho_a c_a d^2), K_face the harmonic mean,
 // B_l = dt h_l / (rho_l c_l), Qs_l = dt (Q_l + h_l (T_a - 37)) / (rho_l c_l),
-// s_p = dt q_p / (rho c) the RF increment and f_p the optional perfusion
-// multiplier.  Damage (Eq. (eq-tissState), T in Kelvin, left point):
+// s_p = dt q_p / (rho c) the RF increment, f_p the optional perfusion
+// multiplier and g_p = exp(-Omega_p) the surviving cell fraction when the
+// perfusion is damage-coupled (Linte's tissue-state factor, Eq.
+// (2675-eq1_Linte) with Omega = ln(c(0)/c(t)) of Eq. (eq-tissState); Omega
+// at the start of the step), else 1.  Damage (Eq. (eq-tissState), T in Kelvin, left point):
 //   Omega' = min(Omega + dt k_a exp(min(c theta / (T_aK + theta), 80)), cap)
 // with T_aK = 310.15 K, k_a = A exp(-Ea / (R T_aK)), c = Ea / (R T_aK).
 #pragma once
@@ -25,13 +28,14 @@
 
 namespace rfa {
 
-// Internal label byte: class index in bits 3-6, flags in bits 0, 1 and 7.
+// Internal label byte: class index in bits 3-6, flags in bits 0, 1, 2 and 7.
 // With the class stored times 8, lab & kClassMask is the byte offset of the
 // class's float2 entry in a row of a coefficient table.
 constexpr unsigned kClassShift = 3;
 constexpr unsigned kClassMask = 0x78u;  // class << kClassShift
 constexpr unsigned kTissue = 0x01u;     // class accumulates damage
 constexpr unsigned kHeld = 0x02u;       // fixed class or outermost layer
+constexpr unsigned kSource = 0x04u;     // RF increment s != 0 (s is read only there)
 constexpr unsigned kLatch = 0x80u;      // t_death reached (sticky)
 constexpr int kMaxClasses = 16;
 
@@ -53,14 +57,29 @@ struct StepConst {
   float clamp2;  // 80 * log2(e)
   float cap;     // Omega cap
   float thr;     // t_death - 37
+  float decay2;  // log2(e) with damage-coupled perfusion, else 0
 };
 
 // Per-thread diagnostic partials of one step.
 struct Partial {
   float perf;     // sum rho c V * (B f theta)       -> J removed by perfusion
   float bnd;      // sum rho c V * conduction term   -> J received from held voxels
-  unsigned mono;  // free voxels whose increment was negative
+  unsigned mono;  // free voxels that cooled by more than kCoolRel |theta| + kCoolAbs
 };
+
+// The cooling-voxel count takes a free voxel as cooling when its
+// float-float state fell by more than kCoolRel |theta| in the step.  The
+// increment's FP32 rounding error is about 10 eps (sum_faces C |d| +
+// |B f theta| + |Qs + s|) (six chained face terms, the float-float
+// differences, the sink, the final sums); where the increment is near zero
+// (conduction, perfusion and source in balance, near the steady state)
+// those magnitudes are at most about 2 |theta| below the step bound, so a
+// smaller fall has an undetermined sign.  kCoolRel = 64 eps leaves a margin
+// of three.  In the far field the temperature excess decays into FP32's
+// subnormal range, where the spacing is absolute (1.4e-45) and the relative
+// bound fails; falls below kCoolAbs = 1e-30 K are not counted either.
+constexpr float kCoolRel = 64.0f / 16777216.0f;  // 2^-18
+constexpr float kCoolAbs = 1e-30f;                // K
 
 // Float-float difference theta_nb - theta, rounded once.
 __device__ __forceinline__ float ff_diff(float hn, float ln, float hi, float lo) {
@@ -78,6 +97,13 @@ __device__ __forceinline__ float ff_diff(float hn, float ln, float hi, float lo)
 // with one or two voxels per lane) and a select that lets the compiler
 // branch around the transcendentals off tissue (kSelectDamage, fewer live
 // registers where each lane carries four voxels).
+//
+// field: pf comes from a perfusion field (kernels with a field; a constant
+// after inlining).  Only those kernels apply the damage coupling: the host
+// gives every damage-coupled grid a field (all ones if none was set).  With
+// the coupling off (K.decay2 = 0) the factor is exp2(-0) = 1 and pf * 1 = pf
+// exactly, for every finite om >= 0 (callers pass a finite damage integral,
+// also into scratch recomputations).
 template <bool kSelectDamage = false>
 __device__ __forceinline__ void voxel_step(
     float hi, float lo, unsigned lab,
@@ -86,7 +112,8 @@ __device__ __forceinline__ void voxel_step(
     float hzm, float lzm, unsigned bzm, float hzp, float lzp, unsigned bzp,
     float s, float pf, float& om, const float2* __restrict__ cf,
     const float4* __restrict__ cls, const StepConst& K,
-    float& nh, float& nl, unsigned& nlab, Partial& acc) {
+    float& nh, float& nl, unsigned& nlab, Partial& acc, bool field = false) {
+  if (field) pf *= __builtin_amdgcn_exp2f(-om * K.decay2);
   // C(l, l_nb) addressed in bytes: row of the own class (16 entries of 8
   // bytes), entry of the neighbour's class (its masked label byte)
   const unsigned row = (lab & kClassMask) << 4;
@@ -143,7 +170,8 @@ __device__ __forceinline__ void voxel_step(
   }
   const bool reached = (nh > K.thr) | ((nh == K.thr) & (nl >= 0.0f));
   nlab = (tissue && reached) ? (lab | kLatch) : lab;
-  acc.mono += (!held && inc < 0.0f) ? 1u : 0u;
+  const float fall = (h2 - hi) + (l2 - lo);  // the state's change, rounded once
+  acc.mono += (!held && fall < -__builtin_fmaf(kCoolRel, fabsf(hi), kCoolAbs)) ? 1u : 0u;
   acc.perf = held ? acc.perf : __builtin_fmaf(c.w, perf, acc.perf);
   acc.bnd = held ? acc.bnd : __builtin_fmaf(c.w, cond, acc.bnd);
 }

@@ -117,8 +117,9 @@ hipError_t launch_field_sums(Grid3 g, double dx, double dy, double dz, const uin
                              hipStream_t st);
 hipError_t launch_source_combine(Grid3 g, const uint8_t* lab, const double* u, int n_tines,
                                  const double* scale, double* q, hipStream_t st);
-// s = dt q / (rho c) on free voxels, 0 on held voxels.
-hipError_t launch_source_increment(Grid3 g, const uint8_t* lab, const double* q,
+// s = dt q / (rho c) on free voxels, 0 on held voxels; the labels' source
+// flag (kSource) set exactly where s != 0.
+hipError_t launch_source_increment(Grid3 g, uint8_t* lab, const double* q,
                                    const ClassParams* cp_dev, double dt, float* s,
                                    hipStream_t st);
 // End-of-call state reduction: {energy J, tmin, tmax, nonfinite count}.
@@ -128,6 +129,9 @@ hipError_t launch_state_reduce(Grid3 g, const uint8_t* lab, const float* hi, con
 // Damage mask and per-class dead counts [n][2].
 hipError_t launch_damage(Grid3 g, const uint8_t* lab, const float* om, uint8_t* mask,
                          unsigned long long* counts, hipStream_t st);
+// *count += voxels whose label has any bit of flag (count zeroed by the caller).
+hipError_t launch_count_flag(Grid3 g, const uint8_t* lab, unsigned flag,
+                             unsigned long long* count, hipStream_t st);
 // Plain streaming copy b = a of n4 float4 (bandwidth ceiling probe).
 hipError_t launch_copy(const float4* a, float4* b, size_t n4, hipStream_t st);
 // The same with non-temporal hints and four float4 per thread per pass.

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_step_naive(StepBuffers b, StepConst K, 
                b.hi_in[pxm], b.lo_in[pxm], b.lab[pxm], b.hi_in[pxp], b.lo_in[pxp], b.lab[pxp],
                b.hi_in[pym], b.lo_in[pym], b.lab[pym], b.hi_in[pyp], b.lo_in[pyp], b.lab[pyp],
                b.hi_in[pzm], b.lo_in[pzm], b.lab[pzm], b.hi_in[pzp], b.lo_in[pzp], b.lab[pzp],
-               s, pf, om, cf, cls, K, nh, nl, nlab, acc);
+               s, pf, om, cf, cls, K, nh, nl, nlab, acc, PERF);
     b.hi_out[p] = nh;
     b.lo_out[p] = nl;
     b.omega[p] = om;
@@ -526,16 +526,40 @@ hipError_t launch_source_write(Grid3 g, double dx, double dy, double dz, const u
   return hipGetLastError();
 }
 
-__global__ void k_source_increment(const uint8_t* lab, const double* q, const ClassParams* cp,
+// s = dt q / (rho c) (0 on held voxels), and the label's source flag set
+// exactly where s != 0: the step kernels read s only on flagged voxels (the
+// RF source beyond its Gaussian cut-off is exactly zero, so most of the grid
+// needs no source bytes).
+__global__ void k_source_increment(uint8_t* lab, const double* q, const ClassParams* cp,
                                    double dt, float* s, size_t n) {
   for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
        p += (size_t)gridDim.x * blockDim.x) {
     const unsigned v = lab[p];
-    s[p] = (v & kHeld) ? 0.0f : (float)(dt * q[p] / cp->rc[class_of(v)]);
+    const float sv = (v & kHeld) ? 0.0f : (float)(dt * q[p] / cp->rc[class_of(v)]);
+    s[p] = sv;
+    const unsigned nv = sv != 0.0f ? (v | kSource) : (v & ~kSource);
+    if (nv != v) lab[p] = (uint8_t)nv;
   }
 }
 
-hipError_t launch_source_increment(Grid3 g, const uint8_t* lab, const double* q,
+// Voxels whose label carries the flag bit(s) `flag`, added into *count.
+__global__ __launch_bounds__(256) void k_count_flag(const uint8_t* lab, unsigned flag, size_t n,
+                                                    unsigned long long* count) {
+  unsigned c = 0;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (size_t)gridDim.x * blockDim.x)
+    c += (lab[p] & flag) ? 1u : 0u;
+  c = wave_sum_u(c);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, (unsigned long long)c);
+}
+
+hipError_t launch_count_flag(Grid3 g, const uint8_t* lab, unsigned flag,
+                             unsigned long long* count, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_flag, dim3(1024), dim3(256), 0, st, lab, flag, g.n(), count);
+  return hipGetLastError();
+}
+
+hipError_t launch_source_increment(Grid3 g, uint8_t* lab, const double* q,
                                    const ClassParams* cp_dev, double dt, float* s,
                                    hipStream_t st) {
   hipLaunchKernelGGL(k_source_increment, dim3(2048), dim3(256), 0, st, lab, q, cp_dev, dt, s,

@@ -8,8 +8,10 @@
 // step, plus the halo ring of the tile.
 //
 // Latency hiding: the loads of plane x + kAhead (own column, halo element,
-// source increment, damage integral) are issued while plane x is computed,
-// into a ring of kSlots register sets.  The x loop is unrolled kSlots times
+// damage integral) are issued while plane x is computed, into a ring of
+// kSlots register sets; the source increment of plane x + kAhead - 1 is
+// loaded with them, only for voxels whose class byte (then in registers)
+// carries the source flag (s is exactly 0 elsewhere).  The x loop is unrolled kSlots times
 // so every ring index is a compile-time constant (no register moves).  One
 // barrier per plane.  Every pass of the unrolled loop computes all kSlots
 // planes and issues the same loads and stores, whatever the chunk length:
@@ -80,12 +82,18 @@ __device__ __forceinline__ void load_plane(const TileCtx& c, int x, bool perf, P
   q.h = ld_f32(c.r.hi_in, c.col * 4, so4);
   q.l = ld_f32(c.r.lo_in, c.col * 4, so4);
   q.b = ld_u8(c.r.lab, c.col, so1);
-  q.s = ld_f32(c.r.src, c.col * 4, sf4);
   q.om = ld_f32(c.r.om, c.col * 4, sf4);
   q.pf = perf ? ld_f32(c.r.perf, c.col * 4, sf4) : 1.0f;
   q.hh = ld_f32(c.r.hi_in, c.hoff * 4, sf4);
   q.hl = ld_f32(c.r.lo_in, c.hoff * 4, sf4);
   q.hb = ld_u8(c.r.lab, c.hoff, sf1);
+}
+
+// Source increment of plane x for a voxel whose class byte (already in q.b)
+// carries the source flag; elsewhere s is exactly 0 and is not read.
+__device__ __forceinline__ void load_src(const TileCtx& c, int x, Plane& q) {
+  const int sf4 = (min(x, c.x1 - 1) - c.xb) * (int)c.psz * 4;  // uniform
+  q.s = ld_f32(c.r.src, (q.b & kSource) ? c.col * 4 : kOob, sf4);
 }
 
 
@@ -240,6 +248,8 @@ __device__ __forceinline__ void march(float2* ts, uint8_t* bs, int cells, float*
   Plane q[kSlots];
 #pragma unroll
   for (int k = 0; k < kAhead; ++k) load_plane(c, x0 + k, perf, q[k]);
+#pragma unroll
+  for (int k = 0; k < kAhead - 1; ++k) load_src(c, x0 + k, q[k]);
 
   Partial acc{0.0f, 0.0f, 0u};
   const int me = lp.me, ys = lp.ys, hcell = lp.hcell;
@@ -252,7 +262,9 @@ __device__ __forceinline__ void march(float2* ts, uint8_t* bs, int cells, float*
     constexpr int BUF = decltype(BUF_)::value;
     constexpr int SN = (S + 1) % kSlots;       // plane x+1
     constexpr int SL = (S + kAhead) % kSlots;  // slot receiving plane x+kAhead
+    constexpr int SS = (S + kAhead - 1) % kSlots;  // plane x+kAhead-1: its source
     load_plane(c, x + kAhead, perf, q[SL]);
+    load_src(c, x + kAhead - 1, q[SS]);
     const Plane& P = q[S];
     float2* t2 = ts + BUF * cells;
     uint8_t* t1 = bs + BUF * cells;
@@ -272,7 +284,7 @@ __device__ __forceinline__ void march(float2* ts, uint8_t* bs, int cells, float*
     const unsigned lab = P.b | (valid ? 0u : kHeld);   // past the chunk: no contributions
     voxel_step(P.h, P.l, lab, hm, lm, bm, N.h, N.l, N.b, ym.x, ym.y, bym, yp.x, yp.y, byp,
                zm.x, zm.y, bzm, zp.x, zp.y, bzp, P.s, P.pf, om, cf, cls, K, nh, nl, nlab,
-               acc);
+               acc, perf);
     {
       const int so = (min(x, c.x1 - 1) - c.xb) * (int)c.psz;  // uniform
       const unsigned v4 = valid ? st4 : kOob;
@@ -366,6 +378,7 @@ __global__ __launch_bounds__(64 * TY) void k_step_batch(const BatchInstance* ins
     K.clamp2 = uf(I.K.clamp2);
     K.cap = uf(I.K.cap);
     K.thr = uf(I.K.thr);
+    K.decay2 = uf(I.K.decay2);
     stage_tables(sm.cf, sm.cls, b.tab, b.n_classes, 64 * TY);
     const int ny = ui(I.ny), nz = ui(I.nz);
     LanePlace lp;

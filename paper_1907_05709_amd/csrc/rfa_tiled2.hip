@@ -196,7 +196,7 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled2(StepBuffers b, StepCons
       Partial p1{0.0f, 0.0f, 0u};
       voxel_step(P.h, P.l, P.b, hm, lm, bm, N.h, N.l, N.b, ym.x, ym.y, bym, yp.x, yp.y, byp,
                  zm.x, zm.y, bzm, zp.x, zp.y, bzp, P.s, P.pf, om1, sm.cf, sm.cls, K, h1, l1, b1,
-                 p1);
+                 p1, PERF);
       const bool own1 = owner && j >= x0 && j < x1;
       acc.perf += own1 ? p1.perf : 0.0f;
       acc.bnd += own1 ? p1.bnd : 0.0f;
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled2(StepBuffers b, StepCons
       Partial p2{0.0f, 0.0f, 0u};
       voxel_step(h1p, l1p, b1p, h1pp, l1pp, b1pp, h1, l1, b1, ym.x, ym.y, bym, yp.x, yp.y, byp,
                  zm.x, zm.y, bzm, zp.x, zp.y, bzp, Q.s, Q.pf, om2, sm.cf, sm.cls, K, h2, l2, b2,
-                 p2);
+                 p2, PERF);
       const int so = (min(max(j - 1, x0), x1 - 1) - xb) * (int)psz;  // uniform
       const unsigned v4 = keep ? col * 4 : kOob;
       st_f32<AUX>(h2, r_hio, v4, so * 4);

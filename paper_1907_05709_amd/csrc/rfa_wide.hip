@@ -20,6 +20,11 @@
 // happen gets an out-of-range offset: no branch surrounds a memory
 // instruction.
 //
+// The source increment is read only where a lane's voxels carry the source
+// flag (kSource: s != 0, set with s; elsewhere s is exactly 0): its load is
+// issued one plane after the plane's other loads, predicated on the class
+// bytes they brought, still a plane before its use.
+//
 // The per-voxel arithmetic is voxel_step() of rfa_device.h, so results are
 // bitwise those of the other step kernels.
 #include <hip/hip_runtime.h>
@@ -195,12 +200,18 @@ __global__ __launch_bounds__(64 * TY, ZV == 2 ? 4 : 1) void k_step_wide(StepBuff
     q.h = ldv<ZV>(r_hi, col * 4, so4);
     q.l = ldv<ZV>(r_lo, col * 4, so4);
     q.b = ldb<ZV>(r_lab, col, so1);
-    q.s = ldv<ZV>(r_src, col * 4, sf4);
     q.om = ldv<ZV>(r_om, col * 4, sf4);
     if constexpr (PERF) q.pf = ldv<ZV>(r_pf, col * 4, sf4);
     q.hh = ldv<ZV>(r_hi, hoff4, sf4);
     q.hl = ldv<ZV>(r_lo, hoff4, sf4);
     q.hb = ldb<ZV>(r_lab, hoff == kOob ? kOob : hoff, sf1);
+  };
+  // source increments of plane x, on lanes whose voxels are flagged (the
+  // class bytes of plane x are in q.b; below x1 they are plane x's own)
+  constexpr unsigned kSrcWord = ZV == 4 ? kSource * 0x01010101u : kSource * 0x0101u;
+  auto load_s = [&](int x, PlaneW<ZV>& q) {
+    const int xf = min(x, x1 - 1) - xb;  // uniform
+    q.s = ldv<ZV>(r_src, (q.b & kSrcWord) ? col * 4 : kOob, xf * (int)psz * 4);
   };
 
   // x-1 neighbours (own voxels) of the plane being computed
@@ -215,6 +226,8 @@ __global__ __launch_bounds__(64 * TY, ZV == 2 ? 4 : 1) void k_step_wide(StepBuff
   PlaneW<ZV> q[kRingW];
 #pragma unroll
   for (int k = 0; k < kAheadW; ++k) load(x0 + k, q[k]);
+#pragma unroll
+  for (int k = 0; k < kAheadW - 1; ++k) load_s(x0 + k, q[k]);
 
   Partial acc{0.0f, 0.0f, 0u};
   const int me = (wy + 1) * RW + ZV + ZV * lane;  // first own LDS cell
@@ -227,8 +240,10 @@ __global__ __launch_bounds__(64 * TY, ZV == 2 ? 4 : 1) void k_step_wide(StepBuff
     constexpr int BUF = SL & 1;
     constexpr int SN = (SL + 1) % kRingW;        // plane x + 1
     constexpr int SA = (SL + kAheadW) % kRingW;  // receives plane x + kAheadW
+    constexpr int SS = (SL + kAheadW - 1) % kRingW;  // plane x + kAheadW - 1
     using LW = LabWord<ZV>;
     load(x + kAheadW, q[SA]);
+    load_s(x + kAheadW - 1, q[SS]);
     const PlaneW<ZV>& P = q[SL];
     *reinterpret_cast<VF*>(&sm.th[BUF][me]) = P.h;
     *reinterpret_cast<VF*>(&sm.tl[BUF][me]) = P.l;
@@ -268,7 +283,7 @@ __global__ __launch_bounds__(64 * TY, ZV == 2 ? 4 : 1) void k_step_wide(StepBuff
       voxel_step<ZV == 4>(P.h[k], P.l[k], lab, hm[k], lm[k], byte_of(bm, k), N.h[k], N.l[k],
                  byte_of(N.b, k), hym[k], lym[k], byte_of(bym, k), hyp[k], lyp[k],
                  byte_of(byp, k), zmh, zml, zmb, zph, zpl, zpb, P.s[k], pf, o, sm.cf, sm.cls,
-                 K, h2, l2, lb2, acc);
+                 K, h2, l2, lb2, acc, PERF);
       nh[k] = h2;
       nl[k] = l2;
       om[k] = o;

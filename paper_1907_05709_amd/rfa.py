@@ -70,6 +70,7 @@ _SIGS = {
     "rfa_set_tissue": [C.c_void_p, C.c_void_p, C.POINTER(rfa_tissue), C.c_int],
     "rfa_set_needle": [C.c_void_p, C.POINTER(rfa_needle)],
     "rfa_set_perfusion": [C.c_void_p, C.c_void_p],
+    "rfa_set_perfusion_decay": [C.c_void_p, C.c_int],
     "rfa_step": [C.c_void_p, C.c_int, C.c_double, C.POINTER(rfa_diag)],
     "rfa_dt_max": [C.c_void_p, C.POINTER(C.c_double)],
     "rfa_damage": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
@@ -213,6 +214,10 @@ def rfa_set_needle(g, needle: rfa_needle):
 
 def rfa_set_perfusion(g, factor_ptr):
     _check(lib().rfa_set_perfusion(g, factor_ptr))
+
+
+def rfa_set_perfusion_decay(g, enable: bool):
+    _check(lib().rfa_set_perfusion_decay(g, int(bool(enable))))
 
 
 def rfa_step(g, n_steps: int, dt: float, want_diag: bool = True):
@@ -490,6 +495,11 @@ class Grid:
             labels = torch.from_numpy(np.ascontiguousarray(labels)).cuda()
         self.set_tissue(labels, case.tissue)
         self.set_needle(case.needle)
+        if getattr(case, "perfusion_decay", False):
+            self.set_perfusion_decay(True)
+
+    def set_perfusion_decay(self, enable: bool = True):
+        rfa_set_perfusion_decay(self.h, enable)
 
     # -- stepping
     def step(self, n_steps: int, dt: float, diag: bool = True):

@@ -16,6 +16,20 @@ from paper_1907_05709_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 N_STEPS, DT, EVERY, M = 60, 0.2, 7, 8
+# Element-wise gradient tolerances.  Against the oracle's FP64 discrete
+# adjoint: 1e-3 relative plus 1e-5 of the largest component (the FP32
+# adjoint's rounding, ~1e-5 relative, is amplified where a component is a
+# sum of contributions of both signs; a tine whose gradient is 1 % of the
+# largest is then held to 2e-3).  Against central differences of the FP32
+# forward (step 1e-3 relative): 1e-3 relative plus 3e-4 of the largest
+# component, the differences' own rounding noise (measured at ~1.5e-4 of
+# the largest gradient at 32^3 and at 128^3).
+ORACLE_RTOL, ORACLE_FLOOR = 1e-3, 1e-5
+FD_RTOL, FD_FLOOR = 1e-3, 3e-4
+
+
+def within(got, want, rtol, floor, scale):
+    return np.abs(got - want) <= rtol * np.abs(want) + floor * scale
 
 
 def coverage(case, omega):
@@ -73,12 +87,23 @@ def test_adjoint_matches_oracle_discrete_adjoint(setup):
     dq, dperf_o = O.adjoint(case, w, n_steps=N_STEPS, dt=DT, q=q, perf=f)
     dP_o = np.tensordot(gt, dq, axes=([1, 2, 3], [0, 1, 2]))
     dc_o = O.bspline_grad(f, dperf_o, M)
-    print("dP gpu", dP, "\ndP oracle", dP_o)
-    assert np.abs(dP - dP_o).max() <= 1e-3 * np.abs(dP_o).max()
-    assert np.linalg.norm(dc - dc_o) <= 1e-3 * np.linalg.norm(dc_o)
+    # element by element: every tine, every control value, every voxel's
+    # perfusion gradient (ORACLE_RTOL relative plus ORACLE_FLOOR of the
+    # largest component)
+    rel_p = np.abs(dP - dP_o) / np.abs(dP_o)
+    rel_c = np.abs(dc - dc_o) / np.abs(dc_o)
+    wc = np.unravel_index(rel_c.argmax(), rel_c.shape)
     big = np.abs(dperf_o) > 1e-3 * np.abs(dperf_o).max()
-    rel = np.abs(dperf[big] - dperf_o[big]) / np.abs(dperf_o[big])
-    assert np.median(rel) < 1e-4 and np.linalg.norm(dperf - dperf_o) <= 1e-3 * np.linalg.norm(dperf_o)
+    rel_f = np.abs(dperf[big] - dperf_o[big]) / np.abs(dperf_o[big])
+    print("dP gpu", dP, "\ndP oracle", dP_o)
+    print(f"worst tine rel {rel_p.max():.2e} (tine {rel_p.argmax()}, |dP| "
+          f"{np.abs(dP_o[rel_p.argmax()]) / np.abs(dP_o).max():.3f} of the largest); worst "
+          f"control value rel {rel_c.max():.2e} at {wc} ({dc[wc]:.4e} vs {dc_o[wc]:.4e}); "
+          f"worst voxel dL/dperf rel {rel_f.max():.2e} over the {int(big.sum())} voxels above "
+          f"1e-3 of the largest")
+    assert within(dP, dP_o, ORACLE_RTOL, ORACLE_FLOOR, np.abs(dP_o).max()).all()
+    assert within(dc, dc_o, ORACLE_RTOL, ORACLE_FLOOR, np.abs(dc_o).max()).all()
+    assert within(dperf, dperf_o, ORACLE_RTOL, ORACLE_FLOOR, np.abs(dperf_o).max()).all()
     g.close()
 
 
@@ -88,21 +113,35 @@ def test_adjoint_matches_central_differences(setup):
     P = case.needle.power.copy()
     L0, w = gpu_loss(g, case, P)
     dP, dc, _ = g.adjoint(w.astype(np.float32), len(P), M)
-    order = np.argsort(-np.abs(dP))
-    for k in order[:3]:
+    # every tine, central differences with a step of 1e-3 relative
+    worst = 0.0
+    for k in range(len(P)):
         h = 1e-3 * P[k]
         Pp, Pm = P.copy(), P.copy()
         Pp[k] += h
         Pm[k] -= h
         fd = (gpu_loss(g, case, Pp)[0] - gpu_loss(g, case, Pm)[0]) / (2 * h)
         print("tine", k, dP[k], fd)
-        assert abs(dP[k] - fd) <= 1e-3 * abs(fd) + 1e-6 * abs(L0) / P[k]
-    # control points: the two with the largest gradient
-    flat = np.argsort(-np.abs(dc).ravel())[:2]
+        worst = max(worst, abs(dP[k] - fd) / abs(fd))
+        assert within(dP[k], fd, FD_RTOL, FD_FLOOR, np.abs(dP).max())
+    print(f"worst tine against central differences: {worst:.2e}")
+    # control values: the three largest gradients, and the two largest among
+    # the control values of the lattice's end spans (index 0, 1, M - 2 or
+    # M - 1 along some axis: the knot spans clamped at the grid's faces),
+    # step 1e-3 max(|c|, 1)
+    mags = np.abs(dc)
+    flat = list(np.argsort(-mags.ravel())[:3])
+    ii = np.indices(dc.shape)
+    outer = ((ii <= 1) | (ii >= M - 2)).any(axis=0).ravel()
+    cand = np.flatnonzero(outer)
+    edge = list(cand[np.argsort(-mags.ravel()[cand])[:2]])
+    assert mags.ravel()[edge].min() > 1e-3 * mags.max()
+    flat += edge
+    worst = 0.0
     for j in flat:
         idx = np.unravel_index(j, dc.shape)
         cp, cm = ctrl.copy(), ctrl.copy()
-        h = np.float32(1e-2)
+        h = np.float32(1e-3 * max(abs(float(ctrl[idx])), 1.0))
         cp[idx] += h
         cm[idx] -= h
         hh = float(cp[idx]) - float(cm[idx])
@@ -112,7 +151,10 @@ def test_adjoint_matches_central_differences(setup):
         Lm = gpu_loss(g, case, P)[0]
         fd = (Lp - Lm) / hh
         print("ctrl", idx, dc[idx], fd)
-        assert abs(dc[idx] - fd) <= 1e-2 * abs(fd)
+        worst = max(worst, abs(dc[idx] - fd) / abs(fd))
+        assert within(dc[idx], fd, FD_RTOL, FD_FLOOR, np.abs(dc).max())
+    print(f"worst control value against central differences: {worst:.2e}")
+    g.set_perfusion_bspline(ctrl)
     g.close()
 
 

@@ -1,0 +1,158 @@
+"""The per-step count of cooling voxels (the monotonicity diagnostic) on the
+GPU, against the FP64 oracle and against geometry.
+
+The paper's claim of a monotone temperature rise under constant heating
+(Sec. "Results") is checked through this count, so it must be shown to
+count.  The cases start from a state that is not an equilibrium (a hot
+field set through rfa_set_temperature, no RF source), so many voxels cool.
+
+The oracle counts every free voxel whose FP64 temperature decreased.  The
+GPU counts a free voxel when its float-float state fell by more than
+2^-18 |theta| + 1e-30 K in the step (theta = T - 37 degC): below that the
+FP32 sign of a near-balanced increment is rounding, not cooling (near the
+steady state conduction, perfusion and source cancel; in the far field the
+excess reaches FP32's subnormal range).  The tests apply the same
+threshold to the oracle's trajectory and compare step by step, allowing
+only the voxels whose oracle fall lies within 1e-6 K of the threshold.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from helpers import box_case
+from oracle import oracle as O
+from paper_1907_05709_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle_built():
+    O.build(force=False)
+
+
+def _grid(case, T0):
+    from paper_1907_05709_amd import rfa
+    g = rfa.Grid(case.shape, case.spacing, t_death=case.t_death, A=case.arrhenius_a,
+                 Ea=case.arrhenius_ea, R=case.gas_r, omega_cap=case.omega_cap)
+    g.set_tissue(case.labels, case.tissue)
+    g.set_needle(None)
+    g.set_temperature(T0)
+    return g
+
+
+COOL_REL, COOL_ABS = 2.0 ** -18, 1e-30
+
+
+def _gpu_counts(g, dt, steps):
+    return [int(g.step(1, dt, diag=True)["mono_violations"]) for _ in range(steps)]
+
+
+def _oracle_counts(tr, fin, free):
+    """Per step: free voxels whose oracle temperature fell by more than
+    COOL_REL |theta| + COOL_ABS, and the voxels within 1e-6 K of that
+    threshold."""
+    after = np.concatenate([tr[1:], fin.T[None]], axis=0)
+    counts, band = [], []
+    for s in range(tr.shape[0]):
+        fall = after[s] - tr[s]
+        thr = -(COOL_REL * np.abs(tr[s] - 37.0) + COOL_ABS)
+        counts.append(int(((fall < thr) & free).sum()))
+        band.append(int(((np.abs(fall - thr) <= 1e-6) & free).sum()))
+    return counts, band
+
+
+def _free(case):
+    held = np.array([t.fixed for t in case.tissue], dtype=bool)[case.labels]
+    f = ~held
+    f[0], f[-1], f[:, 0], f[:, -1], f[:, :, 0], f[:, :, -1] = (False,) * 6
+    return f
+
+
+@pytest.mark.parametrize("h", [0.0, 24306.24])
+def test_hot_cube_first_step_count_is_geometric(h):
+    """A 5^3 cube at 70 degC in a 37 degC box: without perfusion its 98
+    surface voxels cool in the first step, with perfusion all 125."""
+    case = box_case((16, 15, 17), (1e-3,) * 3, h=h, dt=0.05)
+    T0, _, _ = O.initial_state(case)
+    T0 = T0.copy()
+    T0[5:10, 4:9, 6:11] = 70.0
+    g = _grid(case, T0)
+    got = _gpu_counts(g, case.dt, 1)[0]
+    g.close()
+    expect = 125 if h > 0 else 125 - 27
+    assert got == expect, (got, expect)
+
+
+def test_front_around_a_held_cold_block_counts_every_step():
+    """Free voxels at 60 degC around a held 20 degC block, no perfusion or
+    source: in step s the voxels within Manhattan distance s + 1 of the
+    block cool (the oracle's own count is pinned to this geometry); the GPU
+    counts those that fell by more than 2^-18 |theta| (8.8e-5 K here),
+    exactly the oracle trajectory's count under that threshold, which grows
+    with the front."""
+    shape = (22, 21, 23)
+    case = box_case(shape, (0.8e-3, 1e-3, 1.1e-3), h=0.0, dt=0.04, t_boundary=60.0)
+    lo, hi = (9, 8, 10), (12, 13, 12)
+    case.tissue.append(W.Tissue(case.tissue[1].k, 1060.0, 3600.0, 0.0, 0.0, 20.0,
+                                fixed=1, tissue=0))
+    case.labels[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]] = 2
+    T0, om, tm = O.initial_state(case)
+    T0 = np.where(_free(case), 60.0, T0)
+    steps = 6
+    fin, dg, tr = O.run(case, n_steps=steps, q=np.zeros(case.shape),
+                        state=O.State(T0, om, tm), diag=True, trajectory=True)
+    g = _grid(case, T0)
+    got = _gpu_counts(g, case.dt, steps)
+    g.close()
+    want, band = _oracle_counts(tr, fin, _free(case))
+    print("cooling voxels per step: GPU", got, "oracle above the threshold", want,
+          "oracle (any fall)", [int(v) for v in dg[:, 5]], "near the threshold", band)
+    assert dg[0, 5] == 2 * (3 * 5 + 5 * 2 + 2 * 3) and want[0] == dg[0, 5]
+    assert want[-1] > want[0]
+    for s in range(steps):
+        assert abs(got[s] - want[s]) <= band[s], (s, got[s], want[s], band[s])
+
+
+@pytest.mark.parametrize("seed,shape", [(61, (30, 27, 41)), (62, (17, 40, 66))])
+def test_random_hot_field_matches_the_oracle_each_step(seed, shape):
+    """Random classes (a held class among them), a random temperature field
+    between 37 and 90 degC, no source: about half the free voxels cool in
+    every step, and with strong perfusion the count climbs toward every
+    free voxel.  The GPU's count equals the oracle trajectory's count under
+    the same threshold at every step, up to the voxels near the threshold."""
+    case = W.random_tissue_case(seed, shape=shape, n_classes=5, n_tines=1, n_steps=8)
+    free = _free(case)
+    rng = np.random.default_rng(seed)
+    T0, om, tm = O.initial_state(case)
+    T0 = np.where(free, rng.uniform(37.0, 90.0, shape), T0)
+    dt = 0.8 * O.dt_max(case)
+    steps = 8
+    st0 = O.State(T0, om, tm)
+    fin, dg, tr = O.run(case, n_steps=steps, dt=dt, q=np.zeros(case.shape), state=st0,
+                        diag=True, trajectory=True)
+    g = _grid(case, T0)        # no RF source: the needle is not set
+    got = _gpu_counts(g, dt, steps)
+    g.close()
+    want, band = _oracle_counts(tr, fin, free)
+    print("cooling voxels per step: GPU", got, "oracle above the threshold", want,
+          "oracle (any fall)", [int(v) for v in dg[:, 5]], "near the threshold", band)
+    n_free = int(free.sum())
+    assert all(0.2 * n_free < w <= n_free for w in want) and len(set(want)) > 3
+    for s in range(steps):
+        assert abs(got[s] - want[s]) <= band[s], (s, got[s], want[s], band[s])
+
+
+def test_constant_heating_from_equilibrium_has_no_cooling_voxel():
+    """The other side of the count: from the 37 degC equilibrium under a
+    constant source the temperature rises monotonically (Sec. "Results"),
+    the oracle's count is 0 at every step and so is the GPU's."""
+    case = W.case_straight(n=40, n_steps=0, seed=2011)
+    from paper_1907_05709_amd import rfa
+    g = rfa.Grid(case.shape, case.spacing)
+    g.load_case(case)
+    got = _gpu_counts(g, case.dt, 30)
+    g.close()
+    _, dg, _ = O.run(case, n_steps=30, diag=True)
+    assert got == [0] * 30 and int(dg[:, 5].sum()) == 0

@@ -1,0 +1,158 @@
+"""Damage-coupled perfusion on the GPU: the blood-cooling term scaled by the
+surviving cell fraction exp(-Omega) (Linte's tissue-state factor, Eq.
+(2675-eq1_Linte) read through Eq. (eq-tissState)), against the FP64 oracle
+with the same rules as the plain stepper (parity.py), bitwise across the
+step kernels, inside a batch, and refused by the adjoint."""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import parity
+from oracle import oracle as O
+from paper_1907_05709_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle_built():
+    O.build(force=False)
+
+
+def _grid(case, **kw):
+    from paper_1907_05709_amd import rfa
+    g = rfa.Grid(case.shape, case.spacing, t_death=case.t_death, A=case.arrhenius_a,
+                 Ea=case.arrhenius_ea, R=case.gas_r, omega_cap=case.omega_cap, **kw)
+    g.load_case(case)
+    return g
+
+
+def test_coupled_perfusion_straight_64cube_matches_the_oracle():
+    """Heterogeneous liver / tumour / vessels, straight needle, 1000 x 0.01 s
+    with the coupling on: every voxel within 1e-4 K of the oracle, masks and
+    damage integral by the parity rules, diagnostics as for the plain case;
+    the coupling must change the result (dead tissue near the needle loses
+    its cooling and ends warmer)."""
+    base = W.case_straight(n=64, seed=2002)
+    case = dataclasses.replace(base, perfusion_decay=True)
+    q = O.source(case)
+    ost, dg, _ = O.run(case, q=q, diag=True)
+    plain, _, _ = O.run(base, q=q)
+    g = _grid(case)
+    d = g.step(case.n_steps, case.dt, diag=True)
+    T = g.temperature()
+    mask, om, _ = g.damage()
+    g.close()
+    err = parity.compare(case, T, mask, om, ost)
+    gain = float((ost.T - plain.T).max())
+    print(f"coupled perfusion 64^3 x {case.n_steps}: max|dT| = {err:.3e} K, "
+          f"largest warming from the coupling {gain:.3f} K")
+    assert gain > 0.1 and (ost.T - plain.T).min() >= -1e-9
+    scale = abs(dg[:, 1].sum()) + abs(dg[:, 2].sum()) + abs(dg[:, 3].sum())
+    assert abs(d["perfusion_J"] - dg[:, 2].sum()) <= 2e-5 * scale
+    assert abs(d["residual_J"]) <= 1e-5 * scale
+    assert d["mono_violations"] == 0 and int(dg[:, 5].sum()) == 0
+
+
+def test_coupled_perfusion_closed_form_on_the_gpu():
+    """Ea = 0: Omega^n = n dt A everywhere on tissue, so an insulated
+    uniform voxel follows theta0 prod_m (1 - b e^(-m dt A)) and a non-tissue
+    voxel theta0 (1 - b)^n (the oracle's own pin); the GPU must give both
+    within 1e-4 K."""
+    h, A, dt, n, theta0 = 24306.24, 0.3, 0.05, 400, 40.0
+    shape = (9, 10, 11)
+    base = W.case_homogeneous(n=9, n_steps=n, dt=dt)
+    wall = W.Tissue(0.0, 1060.0, 3600.0, 0.0, 0.0, 37.0, fixed=1, tissue=0)
+    tis = W.Tissue(0.0, 1060.0, 3600.0, h, 0.0)
+    non = W.Tissue(0.0, 1060.0, 3600.0, h, 0.0, tissue=0)
+    i, j, k = np.indices(shape)
+    labels = np.where((i + j + k) % 2 == 0, 1, 2).astype(np.uint8)
+    labels[0], labels[-1], labels[:, 0], labels[:, -1] = 0, 0, 0, 0
+    labels[:, :, 0], labels[:, :, -1] = 0, 0
+    case = dataclasses.replace(base, shape=shape, spacing=(1e-3,) * 3, labels=labels,
+                               tissue=[wall, tis, non], needle=None, arrhenius_a=A,
+                               arrhenius_ea=0.0, perfusion_decay=True)
+    T0 = np.where(labels > 0, 37.0 + theta0, 37.0)
+    g = _grid(case)
+    g.set_temperature(T0)
+    g.step(n, dt, diag=False)
+    T = g.temperature()
+    _, om, _ = g.damage()
+    g.close()
+    b = dt * h / (1060.0 * 3600.0)
+    m = np.arange(n)
+    want_t = 37.0 + theta0 * np.prod(1.0 - b * np.exp(-m * dt * A))
+    want_n = 37.0 + theta0 * (1.0 - b) ** n
+    assert np.abs(T[labels == 1] - want_t).max() <= 1e-4
+    assert np.abs(T[labels == 2] - want_n).max() <= 1e-4
+    assert np.allclose(om[labels == 1], n * dt * A, rtol=1e-5)
+
+
+@pytest.mark.parametrize("kw", [dict(kernel=2, depth=1, z_vec=1, tile_y=8, tile_x=5),
+                                dict(kernel=2, depth=1, z_vec=2, tile_y=8, tile_x=4),
+                                dict(kernel=2, depth=1, z_vec=4, tile_y=4, tile_x=6),
+                                dict(kernel=2, depth=2, tile_y=8, tile_x=7)])
+def test_coupled_perfusion_kernels_bitwise_equal_the_reference(kw):
+    """Every tiled step kernel applies the coupling exactly as the
+    one-thread-per-voxel reference kernel (with and without a perfusion
+    field of its own)."""
+    case = dataclasses.replace(
+        W.random_tissue_case(80, shape=(26, 33, 72), n_classes=5, n_tines=2, n_steps=40),
+        perfusion_decay=True)
+    # damage rate 2.3/s at 37 degC rising to ~9/s at 80 degC: Omega spreads
+    # over 0..several within the 40 steps, so exp(-Omega) takes many values
+    case.arrhenius_a, case.arrhenius_ea = 6.0e8, 5.0e4
+    field = np.random.default_rng(81).uniform(0.5, 2.0, case.shape).astype(np.float32)
+    for f in (None, field):
+        g1, g2 = _grid(case, kernel=1), _grid(case, **kw)
+        if f is not None:
+            g1.set_perfusion(f)
+            g2.set_perfusion(f)
+        dt = 0.9 * min(case.dt, g1.dt_max())
+        for n in (1, 6, 33):
+            g1.step(n, dt, diag=False)
+            g2.step(n, dt, diag=False)
+            assert np.array_equal(g1.temperature(), g2.temperature()), n
+            m1, o1, _ = g1.damage()
+            m2, o2, _ = g2.damage()
+            assert np.array_equal(m1, m2) and np.array_equal(o1, o2), n
+        assert o1.max() > 1.0           # the coupling acted
+        g1.close()
+        g2.close()
+
+
+def test_coupled_perfusion_inside_a_batch_and_switched_off():
+    """A coupled grid batched with plain ones equals the same grid stepped
+    alone (bitwise); turning the coupling off gives the plain stepper's
+    state bitwise, and the adjoint refuses a coupled grid."""
+    from paper_1907_05709_amd import rfa
+    cases = [W.case_straight(n=n, n_steps=0, seed=2020 + n) for n in (40, 48, 36)]
+    cases[1] = dataclasses.replace(cases[1], perfusion_decay=True)
+    alone = [_grid(c) for c in cases]
+    batched = [_grid(c) for c in cases]
+    dts = [c.dt for c in cases]
+    b = rfa.Batch(batched, dts)
+    b.step(120)
+    for g, dt in zip(alone, dts):
+        g.step(120, dt, diag=False)
+    for g1, g2 in zip(alone, batched):
+        assert np.array_equal(g1.temperature(), g2.temperature())
+    b.close()
+    plain = _grid(dataclasses.replace(cases[1], perfusion_decay=False))
+    off = _grid(cases[1])
+    off.set_perfusion_decay(False)
+    for g in (plain, off):
+        g.step(120, cases[1].dt, diag=False)
+    assert np.array_equal(plain.temperature(), off.temperature())
+    assert not np.array_equal(plain.temperature(), alone[1].temperature())
+    g = alone[1]
+    g.reset_state()
+    g.forward_checkpointed(10, cases[1].dt, 0)
+    with pytest.raises(rfa.RfaError) as e:
+        g.adjoint(np.zeros(cases[1].shape, np.float32), cases[1].needle.n_tines, 0)
+    assert e.value.status == rfa.RFA_ERR_ARG
+    for g in alone + batched + [plain, off]:
+        g.close()

@@ -138,3 +138,24 @@ def test_insulating_vessel_class_exchanges_no_heat():
             T_free.append(g.raw_state()[0][free])
             g.close()
         assert np.array_equal(T_free[0], T_free[1])
+
+
+def test_overflowing_state_reports_a_numeric_error():
+    """A state whose next step overflows FP32 (two adjacent free voxels at
+    +3e38 and -3e38 degC: their difference is beyond the float range) makes
+    the diagnosed step return RFA_ERR_NUMERIC instead of a silent NaN image;
+    the step without diagnostics does not check.  No fault: the kernels only
+    compute with infinities."""
+    from paper_1907_05709_amd import rfa
+    case = W.case_homogeneous(n=12, n_steps=1)
+    T0 = np.full(case.shape, 37.0)
+    T0[5, 6, 6], T0[6, 6, 6] = 3e38, -3e38
+    g = rfa.Grid(case.shape, case.spacing)
+    g.load_case(case)
+    g.set_temperature(T0)
+    with pytest.raises(rfa.RfaError) as e:
+        g.step(1, case.dt, diag=True)
+    assert e.value.status == rfa.RFA_ERR_NUMERIC
+    assert "non-finite" in str(e.value)
+    assert not np.isfinite(g.temperature()).all()
+    g.close()

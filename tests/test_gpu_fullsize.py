@@ -2,12 +2,16 @@
 bench.py times.
 
 The oracle cannot follow the 256^3 umbrella workload for its 6000 steps
-within a test, so that grid is compared with the oracle over its first
-steps (every voxel, full size, the bench's launch plan) and with the
-reference kernel bitwise; the 64-grid planning sweep is checked bitwise
-against its grids stepped alone; the 128^3 differentiation workload's
-per-tine gradients are checked against central differences of the GPU
-forward at full size."""
+within a test (about 5 minutes on 16 cores), so that grid is compared with
+the oracle over its first steps at every voxel, over its whole horizon on
+the centred 160^3 window (same needle, tissue and time step), and at full
+size over its whole horizon with the reference kernel bitwise and through
+properties that hold at any size (no cooling voxel, maximum principle,
+energy balance).  The 64-grid planning sweep is checked bitwise against its
+grids stepped alone, and its largest umbrella instance against the oracle
+for its full 2000 steps inside the batch; the 128^3 differentiation
+workload's per-tine gradients are checked against central differences of
+the GPU forward at full size."""
 from __future__ import annotations
 
 import numpy as np
@@ -123,16 +127,102 @@ def test_differentiation_128_gradients_match_central_differences():
     om = om.clone().requires_grad_(True)
     (w,) = torch.autograd.grad(coverage_loss(om, labels, vox), om)
     dP, _, _ = g.adjoint(w.float(), len(P), m)
-    for k in np.argsort(-np.abs(dP))[:2]:
-        # The FP32 forward's rounding puts a floor of ~1e-7 L under the loss
-        # differences; at this size a 1e-2 relative step keeps that floor
-        # below the tolerance while the central difference's truncation
-        # error stays ~1e-4 relative (the 32^3 tests use 1e-3).
-        h = 1e-2 * P[k]
+    # every tine, central differences with a step of 1e-3 relative (the
+    # loss is summed in FP64 from the FP32 damage integral)
+    def loss64(powers):
+        return float(loss(powers)[1])
+
+    worst = 0.0
+    for k in range(len(P)):
+        h = 1e-3 * P[k]
         Pp, Pm = P.copy(), P.copy()
         Pp[k] += h
         Pm[k] -= h
-        fd = (float(loss(Pp)[1]) - float(loss(Pm)[1])) / (2 * h)
-        print(f"tine {k}: adjoint {dP[k]:.6e}  central difference {fd:.6e}")
-        assert abs(dP[k] - fd) <= 1e-3 * abs(fd) + 1e-7 * float(L0) / h
+        fd = (loss64(Pp) - loss64(Pm)) / (2 * h)
+        rel = abs(dP[k] - fd) / abs(fd)
+        worst = max(worst, rel)
+        print(f"tine {k}: adjoint {dP[k]:.6e}  central difference {fd:.6e}  rel {rel:.2e}")
+        # 1e-3 relative plus the differences' rounding noise, 3e-4 of the
+        # largest gradient (as at 32^3, tests/test_gpu_adjoint.py)
+        assert abs(dP[k] - fd) <= 1e-3 * abs(fd) + 3e-4 * np.abs(dP).max()
+    print(f"worst tine at 128^3: {worst:.2e}")
     g.close()
+
+
+def test_umbrella_window_160_full_horizon_matches_oracle():
+    """The umbrella workload's needle, tissue and time step for its whole
+    6000 steps (60 s, axis temperatures near 1400 degC, where float-float
+    drift would show) on the centred 160^3 window of its grid, every voxel
+    against the oracle in the launch shape bench.py times at 256^3."""
+    from paper_1907_05709_amd import rfa
+    case = W.case_umbrella_window(160)
+    assert case.n_steps == 6000
+    zv, ty, xc = bench.PLANS[3]
+    g = rfa.Grid(case.shape, case.spacing, depth=1, z_vec=zv, tile_y=ty, tile_x=xc)
+    g.load_case(case)
+    d = g.step(case.n_steps, case.dt, diag=True)
+    T = g.temperature()
+    mask, om, _ = g.damage()
+    g.close()
+    ost, _, _ = O.run(case)
+    err = parity.compare(case, T, mask, om, ost)
+    print(f"umbrella window 160^3 x {case.n_steps}: max|dT| = {err:.3e} K, "
+          f"Tmax = {T.max():.2f}, dead (bit1) voxels {int(((mask & 2) != 0).sum())}")
+    assert T.max() > 1000.0 and d["mono_violations"] == 0
+
+
+def test_umbrella_256_full_horizon_properties():
+    """The full 256^3 umbrella workload for all 6000 steps in the bench's
+    launch plan: bitwise equal to the one-thread-per-voxel reference kernel,
+    no cooling voxel (constant heating from equilibrium), no voxel below
+    37 degC (maximum principle), energy balanced per call to 1e-6 of the
+    injected heat."""
+    from paper_1907_05709_amd import rfa
+    case = W.case_umbrella()
+    zv, ty, xc = bench.PLANS[3]
+    g = rfa.Grid(case.shape, case.spacing, depth=1, z_vec=zv, tile_y=ty, tile_x=xc)
+    ref = rfa.Grid(case.shape, case.spacing, kernel=1)
+    for x in (g, ref):
+        x.load_case(case)
+    worst = 0.0
+    for _ in range(6):
+        d = g.step(case.n_steps // 6, case.dt, diag=True)
+        assert d["mono_violations"] == 0 and d["t_min_C"] >= 37.0
+        worst = max(worst, abs(d["residual_J"]) / d["injected_J"])
+    ref.step(case.n_steps, case.dt, diag=False)
+    for a1, a2 in zip(g.raw_state(), ref.raw_state()):
+        assert np.array_equal(a1, a2)
+    m1, o1, _ = g.damage()
+    m2, o2, _ = ref.damage()
+    assert np.array_equal(m1, m2) and np.array_equal(o1, o2)
+    print(f"umbrella 256^3 x 6000: Tmax {d['t_max_C']:.2f}, worst energy residual "
+          f"{worst:.2e} of the injected heat")
+    assert worst <= 1e-6
+    g.close()
+    ref.close()
+
+
+def test_planning_sweep_largest_umbrella_full_run_in_the_batch_matches_oracle():
+    """The largest 9-tine instance of the 64-grid planning sweep (157^3),
+    stepped inside the full batch for its 2000 steps, against the oracle at
+    every voxel."""
+    from paper_1907_05709_amd import rfa
+    cases = W.planning_sweep(64, n_steps=2000)
+    k = max((c.n_voxels, i) for i, c in enumerate(cases) if c.needle.n_tines == 9)[1]
+    grids = []
+    for c in cases:
+        g = rfa.Grid(c.shape, c.spacing)
+        g.load_case(c)
+        grids.append(g)
+    b = rfa.Batch(grids, [c.dt for c in cases])
+    b.step(2000)
+    b.close()
+    T = grids[k].temperature()
+    mask, om, _ = grids[k].damage()
+    for g in grids:
+        g.close()
+    case = cases[k]
+    ost, _, _ = O.run(case)
+    err = parity.compare(case, T, mask, om, ost)
+    print(f"sweep instance {k} ({'x'.join(map(str, case.shape))}, 9 tines) x 2000 in the "
+          f"batch: max|dT| = {err:.3e} K, Tmax = {T.max():.2f}")
