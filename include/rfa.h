@@ -204,6 +204,21 @@ rfa_status rfa_dt_max(rfa_grid g, double* dt_max);
  * outputs synchronise the grid's stream. */
 rfa_status rfa_damage(rfa_grid g, uint8_t* mask, float* omega, double* dead_m3);
 
+/* rfa_damage for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same outputs, bit for bit, with no hipMalloc, hipFree or other
+ * allocating call.  Its scratch (the per-class dead counters, and the
+ * staging of a host mask) is a static device array of 16 MiB + 256 bytes
+ * that the library holds on every GPU it runs on until the process ends; a
+ * host mask larger than 16 Mi voxels (over 256^3) gives RFA_ERR_ARG (device
+ * masks have no limit).  Every call on a GPU shares that GPU's array, so
+ * calls that overlap on one GPU (other threads, other streams) race; the
+ * counters are cleared by a kernel at the start of each call.  With device
+ * outputs (inputs_on_device) and dead_m3 = NULL the call only enqueues
+ * work on the grid's stream and does not synchronise; host outputs
+ * synchronise. */
+rfa_status rfa_damage_noalloc(rfa_grid g, uint8_t* mask, float* omega, double* dead_m3);
+
 /* Temperature outputs (any may be NULL): the current temperature image, the
  * per-frame output of Alg. 1 and 2 (Sec. "Implementation").  t_C = 37 + hi +
  * lo summed in FP64, degC, [nx*ny*nz] double; hi, lo = the raw float-float

@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -525,12 +526,85 @@ rfa_status finish_diag(rfa_grid g, const double* acc, double e0, double dt, int 
   return RFA_OK;
 }
 
+// ---- allocation-free damage outputs -------------------------------------------
+// Scratch of rfa_damage_noalloc in a file-scope device array: the per-class
+// dead counters (32 x 8 bytes) and the staging of a host mask (up to
+// kNoAllocMaskBytes voxels).  Each device holds its own copy for the life of
+// the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (the array's name is a host
+// stand-in, not a device address).
+constexpr size_t kNoAllocCountBytes = 256;
+constexpr size_t kNoAllocMaskBytes = size_t(16) << 20;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocCountBytes + kNoAllocMaskBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this device's scratch array, looked up once per device
+// with that device current.
+rfa_status scratch_ptr(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(RFA_ERR_ARG, "device %d", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    int prev = 0;
+    HIP_TRY(hipGetDevice(&prev));
+    if (prev != device) HIP_TRY(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != device) (void)hipSetDevice(prev);
+    if (e != hipSuccess || !p)
+      return fail(RFA_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                  hipGetErrorString(e));
+    g_scratch_dev[device] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_dev[device]);
+  return RFA_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
 // C ABI
 // ===========================================================================
 extern "C" {
+
+rfa_status rfa_damage_noalloc(rfa_grid g, uint8_t* mask, float* omega, double* dead_m3) {
+  if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "no tissue");
+  const size_t n = g->g.n();
+  const bool host_mask = mask && !g->opt.inputs_on_device;
+  if (host_mask && n > kNoAllocMaskBytes)
+    return fail(RFA_ERR_ARG, "a host mask of %zu voxels exceeds the %zu-byte scratch", n,
+                kNoAllocMaskBytes);
+  unsigned char* sp = nullptr;
+  rfa_status s = scratch_ptr(g->device, &sp);
+  if (s != RFA_OK) return s;
+  auto* counts = reinterpret_cast<unsigned long long*>(sp);
+  uint8_t* dmask = host_mask ? sp + kNoAllocCountBytes : mask;
+  HIP_TRY(launch_zero_u64(counts, 2 * kMaxClasses, g->st));
+  HIP_TRY(launch_damage(g->g, g->lab, g->om, dmask, counts, g->st));
+  if (host_mask) HIP_TRY(hipMemcpyAsync(mask, dmask, n, hipMemcpyDeviceToHost, g->st));
+  if (omega) HIP_TRY(hipMemcpyAsync(omega, g->om, n * sizeof(float), kind_out(g), g->st));
+  unsigned long long cnt[2 * kMaxClasses] = {};
+  if (dead_m3)
+    HIP_TRY(hipMemcpyAsync(cnt, counts, sizeof cnt, hipMemcpyDeviceToHost, g->st));
+  if (dead_m3 || host_mask || (omega && !g->opt.inputs_on_device))
+    HIP_TRY(hipStreamSynchronize(g->st));
+  if (dead_m3) {
+    const double vol = g->dx * g->dy * g->dz;
+    for (int c = 0; c < g->n_classes; ++c) {
+      dead_m3[2 * c] = (double)cnt[2 * c] * vol;
+      dead_m3[2 * c + 1] = (double)cnt[2 * c + 1] * vol;
+    }
+  }
+  return RFA_OK;
+}
 
 rfa_status rfa_default_options(rfa_options* opt) {
   if (!opt) return fail(RFA_ERR_ARG, "opt is NULL");

@@ -132,6 +132,8 @@ hipError_t launch_damage(Grid3 g, const uint8_t* lab, const float* om, uint8_t* 
 // *count += voxels whose label has any bit of flag (count zeroed by the caller).
 hipError_t launch_count_flag(Grid3 g, const uint8_t* lab, unsigned flag,
                              unsigned long long* count, hipStream_t st);
+// p[0 .. n) = 0 (one small work-group; graph-capturable, unlike a memset).
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
 // Plain streaming copy b = a of n4 float4 (bandwidth ceiling probe).
 hipError_t launch_copy(const float4* a, float4* b, size_t n4, hipStream_t st);
 // The same with non-temporal hints and four float4 per thread per pass.

@@ -659,6 +659,17 @@ hipError_t launch_damage(Grid3 g, const uint8_t* lab, const float* om, uint8_t* 
   return hipGetLastError();
 }
 
+// Counters to zero with a kernel rather than a memset, so that a caller may
+// capture the launch in a graph.
+__global__ __launch_bounds__(64) void k_zero_u64(unsigned long long* p, int n) {
+  for (int i = threadIdx.x; i < n; i += 64) p[i] = 0ull;
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, p, n);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ a,
                                               float4* __restrict__ b, size_t n4) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;

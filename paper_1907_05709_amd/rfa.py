@@ -74,6 +74,7 @@ _SIGS = {
     "rfa_step": [C.c_void_p, C.c_int, C.c_double, C.POINTER(rfa_diag)],
     "rfa_dt_max": [C.c_void_p, C.POINTER(C.c_double)],
     "rfa_damage": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "rfa_damage_noalloc": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "rfa_get_temperature": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "rfa_set_temperature": [C.c_void_p, C.c_void_p],
     "rfa_save_state": [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)],
@@ -563,6 +564,19 @@ class Grid:
         rfa_damage(self.h, _ptr(mask, self.device, np.uint8, True),
                    _ptr(om, self.device, np.float32, True), C.c_void_p(dead.ctypes.data))
         return mask, om, dead.reshape(-1, 2)
+
+    def damage_noalloc(self, want_mask: bool = True, want_omega: bool = True,
+                       want_dead: bool = True):
+        """rfa_damage_noalloc: as damage(), through the allocation-free entry
+        point (outputs not asked for are passed as NULL)."""
+        mask = self._alloc(np.uint8) if want_mask else None
+        om = self._alloc(np.float32) if want_omega else None
+        dead = np.zeros(2 * max(self.n_classes, 1)) if want_dead else None
+        _check(lib().rfa_damage_noalloc(
+            self.h, None if mask is None else _ptr(mask, self.device, np.uint8, True),
+            None if om is None else _ptr(om, self.device, np.float32, True),
+            None if dead is None else C.c_void_p(dead.ctypes.data)))
+        return mask, om, None if dead is None else dead.reshape(-1, 2)
 
     def save_state(self) -> bytes:
         return rfa_save_state(self.h)
