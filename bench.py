@@ -41,13 +41,18 @@ sys.path.insert(0, ROOT)
 METRIC = ("GVoxel-updates/s + % HBM roofline (fwd, fwd+adjoint) vs plain stepper, "
           "ΔT≤1e-4K")
 # Minimum bytes one voxel-step must move through HBM (per step, one pass):
-# float-float state read + write (8 + 8), class byte (1), source increment
-# (4), damage integral read + write (4 + 4).
-BYTES_PER_VOXEL_STEP = 29
+# float-float state read + write (8 + 8), class byte (1), damage integral
+# read + write (4 + 4); plus the source increment (4) on the voxels where it
+# is nonzero (the RF source's support: the kernels skip it elsewhere, where
+# it is exactly 0).  29 B on a voxel of the support, 25 B off it.
+BYTES_PER_VOXEL_STEP = 25
+SOURCE_BYTES = 4
 # Adjoint step with a perfusion field: lambda read + write (4 + 4), theta^n
-# (4), class (1), weight (4), perfusion factor (4), the two accumulators
-# read + write (8 + 8).
-ADJ_BYTES_PER_VOXEL_STEP = 37
+# (4), class (1), weight (4), perfusion factor (4), the perfusion-gradient
+# accumulator read + write (8); plus the source accumulator read + write (8)
+# on the source's support only.
+ADJ_BYTES_PER_VOXEL_STEP = 29
+ADJ_SOURCE_BYTES = 8
 # Adjoint launch on the 128^3 differentiation grid: 8-row tiles of 64 z, 16 x
 # planes per work-group, 256 work-groups.
 ADJ_PLAN = {"rows": 8, "z": 64, "x_planes": 16, "workgroups": 256}
@@ -216,13 +221,15 @@ def run_single(config: int, steps: int, warmup: int, plan_arg: str = "", tune: b
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kms, launches, _ = g.kernel_stats()
+    support = g.source_support()
     copy_gbps = rfa.rfa_copy_bandwidth(1 << 30, 10)
     g.close()
 
     value = case.n_voxels * case.n_steps * steps / wall / 1e9
     avg_ms = kms / launches
-    roof = roofline_dict(BYTES_PER_VOXEL_STEP * case.n_voxels, avg_ms, kernel_name(plan),
-                         launches_timed=launches, copy_ceiling_GBps=round(copy_gbps, 1))
+    roof = roofline_dict(BYTES_PER_VOXEL_STEP * case.n_voxels + SOURCE_BYTES * support, avg_ms,
+                         kernel_name(plan), launches_timed=launches,
+                         copy_ceiling_GBps=round(copy_gbps, 1), source_support_voxels=support)
     roof["traffic"] = traffic_record(config, plan, kernel_name(plan))
     # working set of one step: state in and out, class, source, damage
     ws_mb = case.n_voxels * (16 + 1 + 4 + 4) / 1e6
@@ -366,13 +373,15 @@ def bench_batch(args) -> dict:
     # per launch, algorithmic bytes per launch averaged over the groups
     launches = plan["groups"] * n_steps * args.steps
     avg_launch_ms = dev_ms / launches
-    bytes_per_launch = BYTES_PER_VOXEL_STEP * total_vox / plan["groups"]
+    support = sum(g.source_support() for g in grids)
+    bytes_per_launch = (BYTES_PER_VOXEL_STEP * total_vox + SOURCE_BYTES * support) / plan["groups"]
     copy_gbps = rfa.rfa_copy_bandwidth(1 << 30, 10)
     b.close()
     for g in grids:
         g.close()
     roof = roofline_dict(bytes_per_launch, avg_launch_ms, "k_step_batch",
                          launches_timed=launches, copy_ceiling_GBps=round(copy_gbps, 1),
+                         source_support_voxels=support,
                          note="groups of grids sized to the 256 MB last-level cache run "
                               "their steps back to back; traffic counts bytes below L2, "
                               "which that cache may serve")
@@ -456,16 +465,18 @@ def bench_adjoint(args, steps: int, warmup: int) -> dict:
     kept_value = case.n_voxels * n_steps * steps / kwall / 1e9
     kms, launches, _ = g.kernel_stats()
     adj_ms, adj_launches = g.adjoint_kernel_stats()
+    support = g.source_support()
     copy_gbps = rfa.rfa_copy_bandwidth(1 << 30, 10)
     g.close()
     avg_ms = kms / max(launches, 1)
     adj_avg_ms = adj_ms / max(adj_launches, 1)
     # the perfusion factor field adds one float read per voxel-step
-    fwd = roofline_dict((BYTES_PER_VOXEL_STEP + 4) * case.n_voxels, avg_ms,
-                        kernel_name(plan) + " (forward)", launches_timed=launches)
-    adj = roofline_dict(ADJ_BYTES_PER_VOXEL_STEP * case.n_voxels, adj_avg_ms,
-                        "k_adjoint_tiled (adjoint)", launches_timed=adj_launches,
-                        copy_ceiling_GBps=round(copy_gbps, 1))
+    fwd = roofline_dict((BYTES_PER_VOXEL_STEP + 4) * case.n_voxels + SOURCE_BYTES * support,
+                        avg_ms, kernel_name(plan) + " (forward)", launches_timed=launches,
+                        source_support_voxels=support)
+    adj = roofline_dict(ADJ_BYTES_PER_VOXEL_STEP * case.n_voxels + ADJ_SOURCE_BYTES * support,
+                        adj_avg_ms, "k_adjoint_tiled (adjoint)", launches_timed=adj_launches,
+                        copy_ceiling_GBps=round(copy_gbps, 1), source_support_voxels=support)
     adj["traffic"] = traffic_record(5, ADJ_PLAN, "k_adjoint_tiled",
                                     "traffic_adjoint_differentiation128.json")
     # the dominant kernel (more time in the timed region) carries the roofline

@@ -137,9 +137,10 @@ typedef struct {
   double boundary_J;      /* heat received from held voxels during the call  */
   double residual_J;      /* energy change - (injected - perfusion + boundary)*/
   long long mono_violations; /* sum over steps of free voxels that cooled by
-                                more than 2^-18 |T - 37 degC| in a step (the
-                                check of the monotone rise of Sec. "Results";
-                                smaller falls are FP32 rounding near balance) */
+                                more than 2^-18 |T - 37 degC| + 1e-30 K in a
+                                step (the check of the monotone rise of Sec.
+                                "Results"; smaller falls are FP32 rounding
+                                near balance or in the subnormal range)    */
   double t_min_C, t_max_C;   /* temperature range after the call            */
   long long steps;           /* steps taken by the call                      */
 } rfa_diag;
@@ -265,6 +266,14 @@ rfa_status rfa_load_state(rfa_grid g, const void* buf, size_t bytes);
 
 /* Steps taken since the last rfa_set_tissue / rfa_load_state. */
 rfa_status rfa_get_step_count(rfa_grid g, long long* steps);
+
+/* Voxels on which the RF increment is nonzero after the last step (the
+ * support of the needle's Gaussian line sources, cut where a chord's
+ * density falls below 1e-17 of its peak): the step kernels read the
+ * source field only there, so a step moves 4 * voxels bytes of it rather
+ * than 4 * nx*ny*nz.  RFA_ERR_STATE until a step has followed the last
+ * change of tissue, needle or time step. */
+rfa_status rfa_source_support(rfa_grid g, long long* voxels);
 
 /* Step-kernel timing accumulated since the last call (requires
  * rfa_options.time_kernels): total milliseconds measured with HIP events

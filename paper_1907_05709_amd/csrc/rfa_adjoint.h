@@ -15,8 +15,13 @@ struct AdjointBuffers {
   const float* perf;     // perfusion multiplier, may be null
   const float* w;        // dL/dOmega^N, zeroed where it cannot act
   const Tables* tab;
-  float* sacc;           // += lambda^{n+1}          (dL/ds)
+  float* sacc;           // += lambda^{n+1}          (dL/ds), on the source's support
   float* facc;           // += -B theta^n lambda^{n+1} (dL/df)
+  // sacc is read and written only on voxels flagged kSource (dL/dP needs it
+  // only where a tine's density is nonzero, and is exactly 0 elsewhere);
+  // sacc_all: on every free voxel (when a tine has zero power its density
+  // is nonzero where the flagged increment is not)
+  bool sacc_all;
 };
 
 hipError_t launch_bspline_eval(Grid3 g, const float* ctrl, int m, float* f, hipStream_t st);

@@ -259,13 +259,14 @@ __global__ __launch_bounds__(256) void k_adjoint_step(AdjointBuffers a, StepCons
     nlam[f] = a.lam_in[nb[f]];
     nlab[f] = a.lab[nb[f]];
   }
-  float lo, sa = a.sacc[q], fa = a.facc[q];
+  const bool on_src = a.sacc_all || (lq & kSource) != 0u;
+  float lo, sa = on_src ? a.sacc[q] : 0.0f, fa = a.facc[q];
   const float2* cf = &a.tab->cf[0][0];
   adjoint_voxel(a.lam_in[q], a.theta[q], lq, a.perf ? a.perf[q] : 1.0f, a.w[q], nlam, nlab,
                 [cf](int ax, unsigned cq, unsigned cp) { return pair_from_table(cf, ax, cq, cp); },
                 a.tab->cls, K, lo, sa, fa);
   a.lam_out[q] = lo;
-  a.sacc[q] = sa;
+  if (on_src) a.sacc[q] = sa;
   a.facc[q] = fa;
 }
 
@@ -372,8 +373,14 @@ __global__ __launch_bounds__(64 * TY) void k_adjoint_tiled(AdjointBuffers a, Ste
     q.th = ld_f32(r_th, col * 4, sf4);
     q.w = ld_f32(r_w, col * 4, sf4);
     q.pf = PERF ? ld_f32(r_pf, col * 4, sf4) : 1.0f;
-    q.sa = ld_f32(r_sa, col * 4, sf4);
     q.fa = ld_f32(r_fa, col * 4, sf4);
+  };
+  // the source accumulator of plane x on the source's support, issued one
+  // plane after the plane's other loads (it needs their class byte)
+  const bool sacc_all = a.sacc_all;
+  auto load_sa = [&](int x, AdjPlane& q) {
+    const int sf4 = (min(x, x1 - 1) - xb) * (int)psz * 4;  // uniform
+    q.sa = ld_f32(r_sa, (sacc_all || (q.b & kSource)) ? col * 4 : kOob, sf4);
   };
 
   float lm;  // lambda of the x-1 neighbour (own column)
@@ -386,6 +393,8 @@ __global__ __launch_bounds__(64 * TY) void k_adjoint_tiled(AdjointBuffers a, Ste
   AdjPlane q[kAdjRing];
 #pragma unroll
   for (int k = 0; k < kAdjAhead; ++k) load(x0 + k, q[k]);
+#pragma unroll
+  for (int k = 0; k < kAdjAhead - 1; ++k) load_sa(x0 + k, q[k]);
   const int me = (wy + 1) * W + lane + 1;
   const unsigned st4 = inside ? col * 4 : kOob;
 
@@ -394,7 +403,9 @@ __global__ __launch_bounds__(64 * TY) void k_adjoint_tiled(AdjointBuffers a, Ste
     constexpr int BUF = S & 1;
     constexpr int SN = (S + 1) % kAdjRing;
     constexpr int SA = (S + kAdjAhead) % kAdjRing;
+    constexpr int SS = (S + kAdjAhead - 1) % kAdjRing;
     load(x + kAdjAhead, q[SA]);
+    load_sa(x + kAdjAhead - 1, q[SS]);
     const AdjPlane& P = q[S];
     sm.lam[BUF][me] = P.lam;
     sm.lab[BUF][me] = (uint8_t)P.b;
@@ -416,7 +427,7 @@ __global__ __launch_bounds__(64 * TY) void k_adjoint_tiled(AdjointBuffers a, Ste
     const int so = (min(x, x1 - 1) - xb) * (int)psz * 4;  // uniform
     const unsigned v = valid ? st4 : kOob;
     st_f32(lo, r_out, v, so);
-    st_f32(sa, r_sa, free ? v : kOob, so);
+    st_f32(sa, r_sa, (free && (sacc_all || (P.b & kSource))) ? v : kOob, so);
     st_f32(fa, r_fa, free ? v : kOob, so);
     lm = P.lam;
     bm = P.b;

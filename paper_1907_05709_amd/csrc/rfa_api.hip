@@ -6,6 +6,7 @@
 // rebuilds the per-dt coefficient tables and the source increment when dt
 // changes, and issues every kernel on the grid's stream.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -27,6 +28,15 @@ using namespace rfa;
 namespace {
 
 thread_local std::string g_last_error;
+
+// roctx range around a public call, so rocprofv3 --marker-trace shows the
+// library's calls (rfa_step, rfa_batch_step, ...) around their kernels.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 rfa_status fail(rfa_status s, const char* fmt, ...) {
   char buf[512];
@@ -875,6 +885,7 @@ rfa_status rfa_dt_max(rfa_grid g, double* dt_max) {
 }
 
 rfa_status rfa_step(rfa_grid g, int n_steps, double dt, rfa_diag* diag) {
+  Range range("rfa_step");
   if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
   if (!g->has_tissue) return fail(RFA_ERR_STATE, "set_tissue before step");
   if (n_steps < 0) return fail(RFA_ERR_ARG, "n_steps must be >= 0");
@@ -1066,6 +1077,7 @@ rfa_status warp_impl(rfa_grid g, const float* v, double beta, const float* v2, d
 }  // namespace
 
 rfa_status rfa_warp(rfa_grid g, const float* v, double beta, float* out, double* kernel_ms) {
+  Range range("rfa_warp");
   return warp_impl(g, v, beta, nullptr, 0.0, out, kernel_ms);
 }
 
@@ -1145,12 +1157,14 @@ rfa_status rfa_load_state(rfa_grid g, const void* buf, size_t bytes) {
       bytes < sizeof h + h.payload)
     return fail(RFA_ERR_STATE, "state buffer is for another grid shape");
   if (fnv1a(p, h.payload) != h.checksum) return fail(RFA_ERR_STATE, "state checksum mismatch");
-  // class bits must agree with the current tissue
+  // class, tissue and held bits must agree with the current tissue (the
+  // latch is state; the source flag follows the needle and is rebuilt)
+  constexpr unsigned kFixedBits = kClassMask | kTissue | kHeld;
   std::vector<uint8_t> cur(n);
   HIP_TRY(hipMemcpyAsync(cur.data(), g->lab, n, hipMemcpyDeviceToHost, g->st));
   HIP_TRY(hipStreamSynchronize(g->st));
   for (size_t i = 0; i < n; ++i)
-    if ((cur[i] & 0x7F) != (p[n * 12 + i] & 0x7F))
+    if ((cur[i] & kFixedBits) != (p[n * 12 + i] & kFixedBits))
       return fail(RFA_ERR_STATE, "state buffer was saved with different tissue");
   g->cur = 0;
   HIP_TRY(hipMemcpyAsync(g->hi[0], p, n * 4, hipMemcpyHostToDevice, g->st));
@@ -1160,6 +1174,9 @@ rfa_status rfa_load_state(rfa_grid g, const void* buf, size_t bytes) {
   HIP_TRY(hipStreamSynchronize(g->st));
   g->steps = h.steps;
   g->energy_valid = false;
+  // the saved class bytes carry the source flags of the saving grid's
+  // source: rebuild them with the increment before the next step
+  g->src_dt = -1.0;
   ++g->version;
   return RFA_OK;
 }
@@ -1188,6 +1205,21 @@ rfa_status rfa_kernel_stats(rfa_grid g, double* kernel_ms, long long* launches,
   g->kernel_ms = 0.0;
   g->kernel_launches = 0;
   g->kernel_voxel_steps = 0;
+  return RFA_OK;
+}
+
+rfa_status rfa_source_support(rfa_grid g, long long* voxels) {
+  if (!g || !voxels) return fail(RFA_ERR_ARG, "grid and voxels are required");
+  if (!g->has_tissue) return fail(RFA_ERR_STATE, "no tissue");
+  if (g->src_dt <= 0.0)
+    return fail(RFA_ERR_STATE, "the source increment is built by the first step after a "
+                               "change of tissue, needle or time step");
+  unsigned long long c = 0;
+  HIP_TRY(hipMemsetAsync(g->counts, 0, sizeof c, g->st));
+  HIP_TRY(launch_count_flag(g->g, g->lab, kSource, g->counts, g->st));
+  HIP_TRY(hipMemcpyAsync(&c, g->counts, sizeof c, hipMemcpyDeviceToHost, g->st));
+  HIP_TRY(hipStreamSynchronize(g->st));
+  *voxels = (long long)c;
   return RFA_OK;
 }
 
@@ -1427,6 +1459,7 @@ rfa_status rfa_set_tine_powers(rfa_grid g, const double* power) {
 }
 
 rfa_status rfa_forward_checkpointed(rfa_grid g, int n_steps, double dt, int ckpt_every) {
+  Range range("rfa_forward_checkpointed");
   if (!g) return fail(RFA_ERR_ARG, "grid is NULL");
   if (!g->has_tissue) return fail(RFA_ERR_STATE, "set_tissue before forward");
   if (n_steps < 1 || ckpt_every < 0) return fail(RFA_ERR_ARG, "n_steps >= 1, ckpt_every >= 0");
@@ -1497,6 +1530,7 @@ rfa_status rfa_forward_checkpointed(rfa_grid g, int n_steps, double dt, int ckpt
 
 rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* dL_dctrl,
                        float* dL_dperf) {
+  Range range("rfa_adjoint");
   if (!g || !w_omega) return fail(RFA_ERR_ARG, "grid and w_omega are required");
   if (g->perf_decay)
     return fail(RFA_ERR_ARG, "no adjoint for damage-coupled perfusion (the step is then "
@@ -1546,6 +1580,10 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
   }
   const bool tiled_adj = g->plan.kind != kStepNaive && adjoint_tiled_fits(g->g, adj_xc);
   int lc = 0;
+  // Lambda is accumulated on the flagged source support, unless a tine has
+  // zero power (its density then reaches voxels whose increment is 0)
+  bool sacc_all = false;
+  for (double p : g->power) sacc_all = sacc_all || !(p > 0.0);
   // adjoint step from theta^t = traj[t]
   auto adjoint_step = [&](const float* theta) {
     AdjointBuffers a;
@@ -1558,6 +1596,7 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
     a.tab = g->tab_dev;
     a.sacc = sacc;
     a.facc = facc;
+    a.sacc_all = sacc_all;
     lc = 1 - lc;
     return tiled_adj ? launch_adjoint_tiled(g->g, adj_ty, adj_xc, a, K, g->st)
                      : launch_adjoint_step(g->g, a, K, g->st);
@@ -1915,6 +1954,7 @@ rfa_status rfa_batch_create(int n, const rfa_grid* grids, const double* dt, rfa_
 }
 
 rfa_status rfa_batch_step(rfa_batch b, int n_steps, rfa_diag* diags) {
+  Range range("rfa_batch_step");
   if (!b) return fail(RFA_ERR_ARG, "batch is NULL");
   if (n_steps < 0) return fail(RFA_ERR_ARG, "n_steps must be >= 0");
   if (n_steps == 0) return RFA_OK;

@@ -67,9 +67,9 @@ struct Partial {
   unsigned mono;  // free voxels that cooled by more than kCoolRel |theta| + kCoolAbs
 };
 
-// The cooling-voxel count takes a free voxel as cooling when its
-// float-float state fell by more than kCoolRel |theta| in the step.  The
-// increment's FP32 rounding error is about 10 eps (sum_faces C |d| +
+// The cooling-voxel count takes a free voxel as cooling when its increment
+// is below -(kCoolRel |theta| + kCoolAbs).  The increment's FP32 rounding
+// error is about 10 eps (sum_faces C |d| +
 // |B f theta| + |Qs + s|) (six chained face terms, the float-float
 // differences, the sink, the final sums); where the increment is near zero
 // (conduction, perfusion and source in balance, near the steady state)
@@ -170,8 +170,7 @@ __device__ __forceinline__ void voxel_step(
   }
   const bool reached = (nh > K.thr) | ((nh == K.thr) & (nl >= 0.0f));
   nlab = (tissue && reached) ? (lab | kLatch) : lab;
-  const float fall = (h2 - hi) + (l2 - lo);  // the state's change, rounded once
-  acc.mono += (!held && fall < -__builtin_fmaf(kCoolRel, fabsf(hi), kCoolAbs)) ? 1u : 0u;
+  acc.mono += (!held && inc < -__builtin_fmaf(kCoolRel, fabsf(hi), kCoolAbs)) ? 1u : 0u;
   acc.perf = held ? acc.perf : __builtin_fmaf(c.w, perf, acc.perf);
   acc.bnd = held ? acc.bnd : __builtin_fmaf(c.w, cond, acc.bnd);
 }

@@ -126,12 +126,12 @@ struct WideSmem {
 
 }  // namespace
 
-// Two voxels per lane fit 128 VGPRs (four waves per SIMD) with a perfusion
-// field too, spilling only the partial sums around the plane loop; four
-// voxels per lane keep the compiler's choice (two waves per SIMD), since
-// three would spill inside the loop.
+// Two voxels per lane fit 128 VGPRs (four waves per SIMD); with a perfusion
+// field (and its damage coupling) they would spill there and run three
+// waves per SIMD instead; four voxels per lane keep the compiler's choice
+// (two waves per SIMD).
 template <int ZV, int TY, bool PERF, int AUX>
-__global__ __launch_bounds__(64 * TY, ZV == 2 ? 4 : 1) void k_step_wide(StepBuffers b, StepConst K, int nx,
+__global__ __launch_bounds__(64 * TY, ZV == 2 ? (PERF ? 3 : 4) : 1) void k_step_wide(StepBuffers b, StepConst K, int nx,
                                                        int ny, int nz, int xc, int tiles_z,
                                                        int tiles_y, int nwg) {
   static_assert(TY >= 3, "waves 0-2 load the halo");

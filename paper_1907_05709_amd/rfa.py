@@ -80,6 +80,7 @@ _SIGS = {
     "rfa_save_state": [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)],
     "rfa_load_state": [C.c_void_p, C.c_void_p, C.c_size_t],
     "rfa_get_step_count": [C.c_void_p, C.POINTER(C.c_longlong)],
+    "rfa_source_support": [C.c_void_p, C.POINTER(C.c_longlong)],
     "rfa_kernel_stats": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
                          C.POINTER(C.c_longlong)],
     "rfa_get_plan": [C.c_void_p] + [C.POINTER(C.c_int)] * 6,
@@ -625,6 +626,12 @@ class Grid:
 
     def plan(self) -> dict:
         return rfa_get_plan(self.h)
+
+    def source_support(self) -> int:
+        """rfa_source_support: voxels on which the step reads the source."""
+        v = C.c_longlong()
+        _check(lib().rfa_source_support(self.h, C.byref(v)))
+        return int(v.value)
 
     def tune(self, dt: float, reps: int = 20) -> dict:
         rfa_tune(self.h, dt, reps)

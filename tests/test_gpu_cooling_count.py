@@ -7,8 +7,8 @@ count.  The cases start from a state that is not an equilibrium (a hot
 field set through rfa_set_temperature, no RF source), so many voxels cool.
 
 The oracle counts every free voxel whose FP64 temperature decreased.  The
-GPU counts a free voxel when its float-float state fell by more than
-2^-18 |theta| + 1e-30 K in the step (theta = T - 37 degC): below that the
+GPU counts a free voxel when its FP32 increment is below
+-(2^-18 |theta| + 1e-30 K) in the step (theta = T - 37 degC): below that the
 FP32 sign of a near-balanced increment is rounding, not cooling (near the
 steady state conduction, perfusion and source cancel; in the far field the
 excess reaches FP32's subnormal range).  The tests apply the same

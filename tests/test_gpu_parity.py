@@ -343,3 +343,42 @@ def test_arrhenius_constant_temperature_gpu():
     assert math.isclose(float(om[4, 4, 4]), expect, rel_tol=1e-4)
     assert mask[4, 4, 4] == 3
     g.close()
+
+
+def test_source_flags_follow_the_source():
+    """The step kernels read the RF increment only on voxels whose class byte
+    carries the source flag, rebuilt with the increment.  The support is
+    empty without a needle and part of the grid with one (9 sigma around the
+    needle: much of this small box); a state
+    saved under one needle and restored under another steps exactly as a
+    fresh grid with the second needle (the restored class bytes carry the
+    old flags until the increment is rebuilt)."""
+    import copy
+    from paper_1907_05709_amd import rfa
+    case = W.case_straight(n=48, n_steps=0, seed=2040)
+    other = copy.deepcopy(case)
+    other.needle.pts = other.needle.pts + np.array([3e-3, -2e-3, 1e-3])
+    g = rfa.Grid(case.shape, case.spacing)
+    g.load_case(case)
+    with pytest.raises(rfa.RfaError) as e:        # no step yet: no increment built
+        g.source_support()
+    assert e.value.status == rfa.RFA_ERR_STATE
+    g.step(40, case.dt, diag=False)
+    n1 = g.source_support()
+    assert 0 < n1 < 0.6 * case.n_voxels
+    blob = g.save_state()
+    g.set_needle(other.needle)
+    g.load_state(blob)
+    g.step(60, case.dt, diag=False)
+    ref = rfa.Grid(case.shape, case.spacing, kernel=1)   # reads the source everywhere
+    ref.load_case(other)
+    ref.load_state(blob)
+    ref.step(60, case.dt, diag=False)
+    for a1, a2 in zip(g.raw_state(), ref.raw_state()):
+        assert np.array_equal(a1, a2)
+    assert g.source_support() == ref.source_support() > 0
+    g.set_needle(None)
+    g.step(1, case.dt, diag=False)
+    assert g.source_support() == 0
+    g.close()
+    ref.close()
