@@ -56,6 +56,11 @@ ADJ_SOURCE_BYTES = 8
 # Adjoint launch on the 128^3 differentiation grid: 8-row tiles of 64 z, 16 x
 # planes per work-group, 256 work-groups.
 ADJ_PLAN = {"rows": 8, "z": 64, "x_planes": 16, "workgroups": 256}
+# forward launch plan of the differentiation workload (z voxels per lane,
+# tile rows, x planes): with a perfusion field the step kernel carries one
+# more stream, and 4-row tiles of 8 planes run 12 % faster than the 8-row,
+# 4-plane tiles the plain 128^3 step uses
+ADJ_FWD_PLAN = (2, 4, 8)
 HBM_PEAK_GBPS = 8000.0
 # Step-kernel launches per HIP-event-timed block (one event pair per block).
 # A divisor of the library's 64-step diagnostic reduction period keeps those
@@ -126,10 +131,16 @@ def workload(config: int):
     return case, name
 
 
-def traffic_record(config: int, plan: dict, kernel: str, name: str = ""):
+# committed counter summaries, named for their kernel and workload
+TRAFFIC_FILES = {2: "traffic_step_straight128.json", 3: "traffic_step_umbrella256.json",
+                 4: "traffic_batch_sweep64.json", 5: "traffic_adjoint_differentiation128.json",
+                 6: "traffic_warp_breathing256.json", 7: "traffic_step_yslab256.json"}
+
+
+def traffic_record(config: int, plan: dict, kernel: str):
     """Bytes per launch below L2 from committed rocprofv3 counter summaries,
     if they were taken on the kernel's current sources and launch plan."""
-    path = os.path.join(ROOT, "profiles", name or f"traffic_step_config{config}.json")
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES[config])
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -341,13 +352,14 @@ def bench_batch(args) -> dict:
         g.load_case(c)
         grids.append(g)
     total_vox = sum(c.n_voxels for c in cases)
-    # plain stepper: every grid on its own, one after another
+    # plain stepper: every grid on its own, one after another; both legs
+    # compute the per-step diagnostics, as every other bench step does
     for g, c in zip(grids, cases):
-        g.step(min(n_steps, 20), c.dt, diag=False)
+        g.step(min(n_steps, 20), c.dt, diag=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for g, c in zip(grids, cases):
-        g.step(n_steps, c.dt, diag=False)
+        g.step(n_steps, c.dt, diag=True)
     torch.cuda.synchronize()
     seq_wall = time.perf_counter() - t0
     seq_value = total_vox * n_steps / seq_wall / 1e9
@@ -356,12 +368,12 @@ def bench_batch(args) -> dict:
     if args.tune:
         b.tune(reps=20)
     for _ in range(args.warmup):
-        b.step(n_steps)
+        b.step(n_steps, diag=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dev_ms = 0.0
     for _ in range(args.steps):
-        b.step(n_steps)
+        diag = b.step(n_steps, diag=True)
         ms, _ = b.last_time()
         dev_ms += ms
     torch.cuda.synchronize()
@@ -397,6 +409,12 @@ def bench_batch(args) -> dict:
                    "state": "float-float f32 excess temperature",
                    "plain_stepper_GVox_s": round(seq_value, 3),
                    "batched_speedup_vs_plain": round(value / seq_value, 3)},
+        "diag_last_call": {
+            "t_max_C": round(max(d["t_max_C"] for d in diag), 3),
+            "mono_violations": sum(d["mono_violations"] for d in diag),
+            "worst_residual_of_budget": max(
+                abs(d["residual_J"]) / (abs(d["injected_J"]) + abs(d["perfusion_J"])
+                                        + abs(d["boundary_J"])) for d in diag)},
         "roofline": with_traffic_rate(roof),
     }
     if not args.no_cpu:
@@ -429,7 +447,9 @@ def bench_adjoint(args, steps: int, warmup: int) -> dict:
     n_steps = args.time_steps if args.time_steps > 0 else 600
     case = W.case_differentiation(n_steps=n_steps)
     m, ckpt = 16, 50
-    g = rfa.Grid(case.shape, case.spacing, device=True, time_kernels=TIME_PERIOD)
+    zv, ty, xc = ADJ_FWD_PLAN
+    g = rfa.Grid(case.shape, case.spacing, device=True, time_kernels=TIME_PERIOD, z_vec=zv,
+                 tile_y=ty, tile_x=xc)
     g.load_case(case)
     g.set_perfusion_bspline(np.zeros((m, m, m), np.float32))
     plan = g.plan()
@@ -477,8 +497,7 @@ def bench_adjoint(args, steps: int, warmup: int) -> dict:
     adj = roofline_dict(ADJ_BYTES_PER_VOXEL_STEP * case.n_voxels + ADJ_SOURCE_BYTES * support,
                         adj_avg_ms, "k_adjoint_tiled (adjoint)", launches_timed=adj_launches,
                         copy_ceiling_GBps=round(copy_gbps, 1), source_support_voxels=support)
-    adj["traffic"] = traffic_record(5, ADJ_PLAN, "k_adjoint_tiled",
-                                    "traffic_adjoint_differentiation128.json")
+    adj["traffic"] = traffic_record(5, ADJ_PLAN, "k_adjoint_tiled")
     # the dominant kernel (more time in the timed region) carries the roofline
     dominant, other = (adj, fwd) if adj_ms > kms else (fwd, adj)
     out = {
@@ -620,8 +639,7 @@ def bench_warp(args):
                                            "algorithmic_GBps": round(36 * n / (kf_ms * 1e-3) / 1e9, 1)}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic_record(6, WARP_PLAN, "k_warp",
-                                               "traffic_warp_breathing256.json"),
+                     "traffic": traffic_record(6, WARP_PLAN, "k_warp"),
                      "kernel": "k_warp", "avg_launch_us": round(avg_ms * 1e3, 3),
                      "launches_timed": launches,
                      "bytes_per_launch": bytes_per_launch,

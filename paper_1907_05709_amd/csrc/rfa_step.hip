@@ -122,7 +122,9 @@ StepPlan default_shape(Grid3 g, int kernel, int depth, int tile_y, int tile_x, i
   if (depth == 2 && tiled2_fits(g, 4)) {
     const int ty = tile_y == 16 ? 16 : 8;
     const int tiles = ((g.nz + 61) / 62) * ((g.ny + ty - 3) / (ty - 2));
-    int xc = tile_x ? std::min(tile_x, g.nx) : default_xc(g, tiles);
+    // the x-march runs planes x0 - 1 .. x0 + xc four at a time: xc = 2 mod 4
+    // leaves no pass over planes outside the chunk
+    int xc = tile_x ? std::min(tile_x, g.nx) : std::min(g.nx, default_xc(g, tiles) + 2);
     while (xc > 4 && !tiled2_fits(g, xc)) xc /= 2;
     return plan_tiled2(g, ty, xc);
   }
@@ -164,8 +166,9 @@ int plan_candidates(Grid3 g, int max_depth, StepPlan* out, int max_out) {
       }
   if (max_depth < 2) return n;
   const int tys2[] = {8, 16};
+  const int xcs2[] = {6, 14, 30, 62};  // 2 mod 4: no pass outside the chunk
   for (int ty : tys2)
-    for (int xc : xcs) {
+    for (int xc : xcs2) {
       if (n >= max_out) return n;
       if ((xc > g.nx && xc != 4) || !tiled2_fits(g, std::min(xc, g.nx))) continue;
       out[n++] = plan_tiled2(g, ty, std::min(xc, g.nx));

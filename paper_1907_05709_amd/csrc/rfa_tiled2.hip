@@ -92,6 +92,8 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled2(StepBuffers b, StepCons
   const int y = y0 + wy;
   const bool in_grid = z >= 0 && z < nz && y >= 0 && y < ny;
   const bool owner = in_grid && lane >= 1 && lane <= kInnerZ && wy >= 1 && wy <= TY - 2;
+  const int wy_u = __builtin_amdgcn_readfirstlane(wy);
+  const bool inner_row = wy_u >= 1 && wy_u <= TY - 2;  // uniform per wave
   const int x0 = tx * xc;
   const int x1 = min(x0 + xc, nx);
   const int xb = max(x0 - 2, 0);          // first plane the descriptors cover
@@ -204,20 +206,24 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled2(StepBuffers b, StepCons
     }
 
     // second step, plane j - 1, stored by the owners while it lies in the
-    // chunk (every pass issues the same memory instructions; see below)
+    // chunk (every pass issues the same memory instructions; see below).
+    // The footprint's first and last rows own nothing: their waves skip the
+    // arithmetic (a wave-uniform branch around LDS reads and VALU only).
     {
       const bool keep = owner && j > x0 && j <= x1;
-      const float2 ym = sm.t1[1 - BUF][me - W], yp = sm.t1[1 - BUF][me + W];
-      const float2 zm = sm.t1[1 - BUF][me - 1], zp = sm.t1[1 - BUF][me + 1];
-      const unsigned bym = sm.b1[1 - BUF][me - W], byp = sm.b1[1 - BUF][me + W];
-      const unsigned bzm = sm.b1[1 - BUF][me - 1], bzp = sm.b1[1 - BUF][me + 1];
       const Plane2& Q = q[SP];
-      float h2, l2, om2 = om1p;
-      unsigned b2;
+      float h2 = h1p, l2 = l1p, om2 = om1p;
+      unsigned b2 = b1p;
       Partial p2{0.0f, 0.0f, 0u};
-      voxel_step(h1p, l1p, b1p, h1pp, l1pp, b1pp, h1, l1, b1, ym.x, ym.y, bym, yp.x, yp.y, byp,
-                 zm.x, zm.y, bzm, zp.x, zp.y, bzp, Q.s, Q.pf, om2, sm.cf, sm.cls, K, h2, l2, b2,
-                 p2, PERF);
+      if (inner_row) {
+        const float2 ym = sm.t1[1 - BUF][me - W], yp = sm.t1[1 - BUF][me + W];
+        const float2 zm = sm.t1[1 - BUF][me - 1], zp = sm.t1[1 - BUF][me + 1];
+        const unsigned bym = sm.b1[1 - BUF][me - W], byp = sm.b1[1 - BUF][me + W];
+        const unsigned bzm = sm.b1[1 - BUF][me - 1], bzp = sm.b1[1 - BUF][me + 1];
+        voxel_step(h1p, l1p, b1p, h1pp, l1pp, b1pp, h1, l1, b1, ym.x, ym.y, bym, yp.x, yp.y,
+                   byp, zm.x, zm.y, bzm, zp.x, zp.y, bzp, Q.s, Q.pf, om2, sm.cf, sm.cls, K, h2,
+                   l2, b2, p2, PERF);
+      }
       const int so = (min(max(j - 1, x0), x1 - 1) - xb) * (int)psz;  // uniform
       const unsigned v4 = keep ? col * 4 : kOob;
       st_f32<AUX>(h2, r_hio, v4, so * 4);

@@ -174,7 +174,7 @@ def test_batch_diagnostics_match_single_grids(group_voxels, layout):
         scale = abs(db["injected_J"]) + abs(db["perfusion_J"]) + abs(db["boundary_J"])
         for k in ("perfusion_J", "boundary_J"):
             assert abs(ds[k] - db[k]) <= 1e-6 * scale, (k, ds[k], db[k], scale)
-        assert abs(db["residual_J"]) <= 1e-5 * scale
+        assert abs(db["residual_J"]) <= 1e-6 * scale   # energy balance to FP32 partial-sum rounding
     b.close()
     for g in singles + batched:
         g.close()

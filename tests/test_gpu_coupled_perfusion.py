@@ -53,7 +53,7 @@ def test_coupled_perfusion_straight_64cube_matches_the_oracle():
     assert gain > 0.1 and (ost.T - plain.T).min() >= -1e-9
     scale = abs(dg[:, 1].sum()) + abs(dg[:, 2].sum()) + abs(dg[:, 3].sum())
     assert abs(d["perfusion_J"] - dg[:, 2].sum()) <= 2e-5 * scale
-    assert abs(d["residual_J"]) <= 1e-5 * scale
+    assert abs(d["residual_J"]) <= 1e-6 * scale   # energy balance to FP32 partial-sum rounding
     assert d["mono_violations"] == 0 and int(dg[:, 5].sum()) == 0
 
 

@@ -31,7 +31,7 @@ def _check_diag(d, od, rtol=2e-5):
     assert math.isclose(d["energy_J"], od["energy"], rel_tol=rtol)
     assert abs(d["perfusion_J"] - od["perfusion"]) <= rtol * scale
     assert abs(d["boundary_J"] - od["boundary"]) <= rtol * scale
-    assert abs(d["residual_J"]) <= 1e-5 * scale
+    assert abs(d["residual_J"]) <= 1e-6 * scale   # energy balance to FP32 partial-sum rounding
     assert math.isclose(d["t_max_C"], od["tmax"], abs_tol=1e-4)
     assert math.isclose(d["t_min_C"], od["tmin"], abs_tol=1e-4)
 
