@@ -1698,6 +1698,7 @@ struct rfa_batch_s {
   int* first_dev = nullptr;
   float* partials = nullptr;        // [kPartialSlots][n_items][3]
   double* dacc = nullptr;           // [n][3]
+  double* slot_acc = nullptr;       // [n][kPartialSlots][3] reduction scratch
   int n_items = 0;
   int ty = 4;
   int xc = 8;
@@ -1742,11 +1743,13 @@ void batch_free_device(rfa_batch b) {
   f(b->first_dev);
   f(b->partials);
   f(b->dacc);
+  f(b->slot_acc);
   b->inst_dev = nullptr;
   b->items_dev = nullptr;
   b->first_dev = nullptr;
   b->partials = nullptr;
   b->dacc = nullptr;
+  b->slot_acc = nullptr;
 }
 
 // (Re)build the device descriptor table and work list from the grids'
@@ -1822,7 +1825,8 @@ rfa_status batch_build(rfa_batch b) {
   if ((s = dmalloc(&b->inst_dev, n)) || (s = dmalloc(&b->items_dev, items.size())) ||
       (s = dmalloc(&b->first_dev, 2 * (size_t)n)) ||
       (s = dmalloc(&b->partials, (size_t)kPartialSlots * b->n_items * 3)) ||
-      (s = dmalloc(&b->dacc, 3 * (size_t)n)))
+      (s = dmalloc(&b->dacc, 3 * (size_t)n)) ||
+      (s = dmalloc(&b->slot_acc, (size_t)kPartialSlots * 3 * n)))
     return s;
   HIP_TRY(hipMemcpyAsync(b->inst_dev, b->inst.data(), n * sizeof(BatchInstance),
                          hipMemcpyHostToDevice, b->st));
@@ -1880,13 +1884,14 @@ rfa_status batch_graph(rfa_batch b, int n_steps, bool diag, hipGraphExec_t* out)
                               wg_perf, par, part, b->st);
       if (e == hipSuccess && diag && ++pending == kPartialSlots) {
         e = launch_reduce_batch(b->partials, pending, b->n_items, b->first_dev, G.inst0,
-                                G.inst1 - G.inst0, b->dacc, b->st);
+                                G.inst1 - G.inst0, b->slot_acc, kPartialSlots, b->dacc,
+                                b->st);
         pending = 0;
       }
     }
     if (e == hipSuccess && diag && pending > 0)
       e = launch_reduce_batch(b->partials, pending, b->n_items, b->first_dev, G.inst0,
-                              G.inst1 - G.inst0, b->dacc, b->st);
+                              G.inst1 - G.inst0, b->slot_acc, kPartialSlots, b->dacc, b->st);
   }
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->st, &graph);

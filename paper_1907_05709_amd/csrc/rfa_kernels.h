@@ -80,10 +80,11 @@ hipError_t launch_reduce_partials(const float* partials, int n_slots, int nwg,
 
 // Per-instance sums of batch partials [n_slots][n_items][3] for instances
 // inst0 .. inst0 + n_inst - 1: instance i owns items [first[2 i],
-// first[2 i + 1]); acc[3 i + c] += its sum.
+// first[2 i + 1]); acc[3 i + c] += its sum.  slot_acc is scratch of
+// [instances][slot_stride][3] doubles (n_slots <= slot_stride <= 64).
 hipError_t launch_reduce_batch(const float* partials, int n_slots, int n_items,
-                               const int* first, int inst0, int n_inst, double* acc,
-                               hipStream_t st);
+                               const int* first, int inst0, int n_inst, double* slot_acc,
+                               int slot_stride, double* acc, hipStream_t st);
 
 // ---- setup ---------------------------------------------------------------
 // Build internal label bytes from class labels; counts labels >= n_classes.

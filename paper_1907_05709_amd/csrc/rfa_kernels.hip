@@ -206,21 +206,24 @@ hipError_t launch_reduce_partials(const float* partials, int n_slots, int nwg, d
   return hipGetLastError();
 }
 
-// Batched diagnostics: block i sums, in fixed order, the partials of
-// instance i's items over n_slots steps into acc[3 i .. 3 i + 2].
-__global__ __launch_bounds__(256) void k_reduce_batch(const float* partials, int n_slots,
-                                                      int n_items, const int* first, int inst0,
-                                                      double* acc) {
+// Batched diagnostics in two fixed-order passes: block (i, s) sums the
+// partials of instance i's items in step slot s into slot_acc[i][s][.]
+// (its threads stride over the items, then wave and work-group sums), and
+// block i of the second pass adds its n_slots slot sums (one lane each, a
+// wave sum) to acc[3 i .. 3 i + 2].  Every instance and slot gets its own
+// work-group, so the pass is as wide as the batch.
+__global__ __launch_bounds__(256) void k_reduce_batch_slots(const float* partials, int n_items,
+                                                            const int* first, int inst0,
+                                                            int slot_stride, double* slot_acc) {
   __shared__ double sh[3][4];
-  const int i = inst0 + blockIdx.x;
+  const int i = inst0 + blockIdx.x, s = blockIdx.y;
   const int a = first[2 * i], cnt = first[2 * i + 1] - first[2 * i];
+  const float* p = partials + ((size_t)s * n_items + a) * 3;
   double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-  for (int e = threadIdx.x; e < n_slots * cnt; e += 256) {
-    const int s = e / cnt, k = e - s * cnt;
-    const float* p = partials + ((size_t)s * n_items + a + k) * 3;
-    v0 += (double)p[0];
-    v1 += (double)p[1];
-    v2 += (double)p[2];
+  for (int k = threadIdx.x; k < cnt; k += 256) {
+    v0 += (double)p[3 * k];
+    v1 += (double)p[3 * k + 1];
+    v2 += (double)p[3 * k + 2];
   }
   v0 = wave_sum_d(v0);
   v1 = wave_sum_d(v1);
@@ -233,15 +236,35 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const float* partials, int
   }
   __syncthreads();
   if (threadIdx.x < 3)
-    acc[3 * i + threadIdx.x] += ((sh[threadIdx.x][0] + sh[threadIdx.x][1]) +
-                                 (sh[threadIdx.x][2] + sh[threadIdx.x][3]));
+    slot_acc[((size_t)i * slot_stride + s) * 3 + threadIdx.x] =
+        (sh[threadIdx.x][0] + sh[threadIdx.x][1]) + (sh[threadIdx.x][2] + sh[threadIdx.x][3]);
+}
+
+__global__ __launch_bounds__(64) void k_reduce_batch_final(const double* slot_acc, int n_slots,
+                                                           int inst0, int slot_stride,
+                                                           double* acc) {
+  const int i = inst0 + blockIdx.x, s = threadIdx.x;
+  const double* q = slot_acc + ((size_t)i * slot_stride + s) * 3;
+  const bool on = s < n_slots;
+  const double v0 = wave_sum_d(on ? q[0] : 0.0);
+  const double v1 = wave_sum_d(on ? q[1] : 0.0);
+  const double v2 = wave_sum_d(on ? q[2] : 0.0);
+  if (s == 0) {
+    acc[3 * i] += v0;
+    acc[3 * i + 1] += v1;
+    acc[3 * i + 2] += v2;
+  }
 }
 
 hipError_t launch_reduce_batch(const float* partials, int n_slots, int n_items,
-                               const int* first, int inst0, int n_inst, double* acc,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_batch, dim3(n_inst), dim3(256), 0, st, partials, n_slots,
-                     n_items, first, inst0, acc);
+                               const int* first, int inst0, int n_inst, double* slot_acc,
+                               int slot_stride, double* acc, hipStream_t st) {
+  if (n_inst <= 0 || n_slots <= 0) return hipSuccess;
+  if (n_slots > slot_stride || slot_stride > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce_batch_slots, dim3(n_inst, n_slots), dim3(256), 0, st, partials,
+                     n_items, first, inst0, slot_stride, slot_acc);
+  hipLaunchKernelGGL(k_reduce_batch_final, dim3(n_inst), dim3(64), 0, st, slot_acc, n_slots,
+                     inst0, slot_stride, acc);
   return hipGetLastError();
 }
 

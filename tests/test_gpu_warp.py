@@ -4,12 +4,14 @@ max |T_view - T_oracle| <= 1e-4 K.
 
 Where the kernel's error comes from (eps = 2^-24), printed beside each
 check: the output is rounded once (<= eps |T|); the lerps act on corner
-excesses over the cell's first corner (<= ~10 eps D, D the largest such
+excesses over the cell's nearest corner (<= ~10 eps D, D the largest such
 excess, a few K); the fraction within the cell is rounded to float once per
 axis (<= eps / 2 voxel times the neighbour difference G_a along that axis);
-sample positions are FP64.  On voxel centres (zero surrogate, integer
-shifts, positions clamped to a wall) the view is the float-float state
-rounded once to float, bit for bit."""
+sample positions are float-float (~2^-47 relative).  Below 1024 degC a cell
+reads the lo word of its nearest corner only (each dropped lo word is at
+most ulp(hi) / 2 <= 3.1e-5 K); hotter cells read all eight.  On voxel
+centres (zero surrogate, integer shifts, positions clamped to a wall) the
+view is the float-float state rounded once to float, bit for bit."""
 from __future__ import annotations
 
 import numpy as np
@@ -72,6 +74,28 @@ def test_warp_matches_oracle(shape, beta):
     err = np.abs(out.astype(np.float64) - ref).max()
     print(shape, beta, "max err", err, "rounding estimate", bound(T))
     assert out.dtype == np.float32 and err <= GATE
+    g.close()
+
+
+@pytest.mark.parametrize("beta", [1.0, 0.0])
+def test_hot_cells_read_every_lo_word(beta):
+    """A needle-hot core above 1024 degC (cells there read all eight lo
+    words) in a cooler periphery (nearest corner's lo word only): within the
+    gate everywhere, and bit for bit the rounded state on voxel centres."""
+    shape, spacing = (40, 37, 66), (0.6e-3, 0.7e-3, 0.5e-3)
+    T = W.hot_field(shape, spacing, peak_c=1500.0, sigma_m=4e-3, seed=6250)
+    assert T.max() > 1300.0 and np.mean(T < 1000.0) > 0.5
+    v = W.breathing_field(shape, spacing, amplitude_m=3e-3, seed=6251)
+    g = _grid(shape, spacing)
+    g.set_temperature(T)
+    out = g.warp(v, beta)
+    ref = warp_oracle(T, v, spacing, beta)
+    err = np.abs(out.astype(np.float64) - ref).max()
+    print("hot core max err", err, "rounding estimate", bound(T))
+    assert err <= GATE
+    if beta == 0.0:
+        hi, lo = g.raw_state()
+        assert np.array_equal(out, rounded_state(hi, lo))
     g.close()
 
 
