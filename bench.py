@@ -560,7 +560,7 @@ def cpu_baseline_adjoint() -> dict:
 # (here the walls' zero-displacement voxels, under 2 %), not counted
 WARP_BYTES_PER_VOXEL = 20
 WARP2_BYTES_PER_VOXEL = 32  # two fields
-WARP_PLAN = {"threads": 256, "x_voxels_per_thread": 4}
+WARP_PLAN = {"threads": 256, "tile_z": 64, "tile_y": 4, "x_voxels_per_thread": 4}
 WARP_FRAMES_PER_CYCLE = 100
 
 
