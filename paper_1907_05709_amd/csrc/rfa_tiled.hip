@@ -7,9 +7,11 @@
 // neighbours from registers.  Each voxel's state is read from HBM once per
 // step, plus the halo ring of the tile.
 //
-// Latency hiding: the loads of plane x + kAhead (own column, halo element,
+// Latency hiding: the loads of plane x + AHEAD (own column, halo element,
 // damage integral) are issued while plane x is computed, into a ring of
-// kSlots register sets; the source increment of plane x + kAhead - 1 is
+// kSlots register sets (AHEAD = 3 in the single-grid kernel; 2 in the batch
+// kernel, whose 64 registers let eight waves per SIMD hide the rest, +5 %
+// on the planning sweep); the source increment of plane x + AHEAD - 1 is
 // loaded with them, only for voxels whose class byte (then in registers)
 // carries the source flag (s is exactly 0 elsewhere).  The x loop is unrolled kSlots times
 // so every ring index is a compile-time constant (no register moves).  One
@@ -48,8 +50,8 @@ namespace {
 
 using namespace tile;
 
-constexpr int kAhead = 3;           // planes in flight ahead of the computed one
-constexpr int kSlots = kAhead + 1;  // register ring size
+constexpr int kAhead = 3;  // planes in flight ahead of the computed one (at most)
+constexpr int kSlots = 4;  // register ring size
 
 // Registers of one plane for one thread.
 struct Plane {
@@ -209,7 +211,7 @@ __device__ __forceinline__ LanePlace flat_place(int ny, int nz, int t) {
 // must be staged (a barrier inside the march orders them).  The
 // work-group's partial sums are written to partials[wg_slot * 3] if
 // partials is not null.
-template <int NT, int AUX>
+template <int NT, int AUX, int AHEAD = kAhead>
 __device__ __forceinline__ void march(float2* ts, uint8_t* bs, int cells, float* red,
                                       const float2* cf, const float4* cls,
                                       const StepBuffers& b, const StepConst& K, bool perf,
@@ -245,11 +247,12 @@ __device__ __forceinline__ void march(float2* ts, uint8_t* bs, int cells, float*
     lm = ld_f32(c.r.lo_in, c.col * 4, so * 4);
     bm = ld_u8(c.r.lab, c.col, so);
   }
+  static_assert(AHEAD >= 1 && AHEAD < kSlots && AHEAD <= kAhead, "ring depth");
   Plane q[kSlots];
 #pragma unroll
-  for (int k = 0; k < kAhead; ++k) load_plane(c, x0 + k, perf, q[k]);
+  for (int k = 0; k < AHEAD; ++k) load_plane(c, x0 + k, perf, q[k]);
 #pragma unroll
-  for (int k = 0; k < kAhead - 1; ++k) load_src(c, x0 + k, q[k]);
+  for (int k = 0; k < AHEAD - 1; ++k) load_src(c, x0 + k, q[k]);
 
   Partial acc{0.0f, 0.0f, 0u};
   const int me = lp.me, ys = lp.ys, hcell = lp.hcell;
@@ -261,10 +264,10 @@ __device__ __forceinline__ void march(float2* ts, uint8_t* bs, int cells, float*
     constexpr int S = decltype(S_)::value;
     constexpr int BUF = decltype(BUF_)::value;
     constexpr int SN = (S + 1) % kSlots;       // plane x+1
-    constexpr int SL = (S + kAhead) % kSlots;  // slot receiving plane x+kAhead
-    constexpr int SS = (S + kAhead - 1) % kSlots;  // plane x+kAhead-1: its source
-    load_plane(c, x + kAhead, perf, q[SL]);
-    load_src(c, x + kAhead - 1, q[SS]);
+    constexpr int SL = (S + AHEAD) % kSlots;      // slot receiving plane x+AHEAD
+    constexpr int SS = (S + AHEAD - 1) % kSlots;  // plane x+AHEAD-1: its source
+    load_plane(c, x + AHEAD, perf, q[SL]);
+    load_src(c, x + AHEAD - 1, q[SS]);
     const Plane& P = q[S];
     float2* t2 = ts + BUF * cells;
     uint8_t* t1 = bs + BUF * cells;
@@ -332,12 +335,13 @@ __global__ __launch_bounds__(64 * TY) void k_step_tiled(StepBuffers b, StepConst
 
 // Batched step over the work list of all instances (items grouped by
 // instance).  LOOP: a persistent grid walks the list round-robin; otherwise
-// one work-group per item, in XCD-aware order.  FLAT: items are flat plane
+// one work-group per item, in XCD-aware order, at eight waves per SIMD (64
+// registers with a ring two planes deep, no spills).  FLAT: items are flat plane
 // segments of 64 TY voxels (item tz = segment), else 2.5-D tiles.  Each
 // item stages its instance's tables before its march.  parity selects the
 // ping-pong image.
 template <int TY, bool PERF, bool LOOP, bool FLAT>
-__global__ __launch_bounds__(64 * TY) void k_step_batch(const BatchInstance* inst,
+__global__ __launch_bounds__(64 * TY, PERF || LOOP ? 1 : 8) void k_step_batch(const BatchInstance* inst,
                                                         const BatchItem* items, int first_item,
                                                         int n_items, int parity,
                                                         float* partials) {
@@ -387,9 +391,9 @@ __global__ __launch_bounds__(64 * TY) void k_step_batch(const BatchInstance* ins
     else
       lp = tile_place<TY>(ny, nz, ui(w.tz), ui(w.ty));
     // groups of a batch are sized to stay in the last-level cache
-    march<TY, kStoreBack>(&sm.ts[0][0], &sm.bs[0][0], Smem::CELLS + 1, &sm.red[0][0], sm.cf,
-                          sm.cls, b, K, PERF, ui(I.nx), ny, nz, ui(I.xc), ui(w.tx), lp,
-                          partials, it);
+    march<TY, kStoreBack, 2>(&sm.ts[0][0], &sm.bs[0][0], Smem::CELLS + 1, &sm.red[0][0],
+                             sm.cf, sm.cls, b, K, PERF, ui(I.nx), ny, nz, ui(I.xc), ui(w.tx),
+                             lp, partials, it);
   };
   if (LOOP) {
     for (int k = blockIdx.x; k < n_items; k += gridDim.x) {
