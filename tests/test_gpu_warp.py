@@ -174,6 +174,33 @@ def test_full_size_device_warp_matches_oracle():
     g.close()
 
 
+def test_warp_beyond_buffer_offsets_matches_oracle():
+    """A grid whose rows are longer than 2^24 voxels takes the kernel's
+    path without buffer descriptors (64-bit addresses, full-width index
+    products): same tolerance, same exact voxel centres."""
+    shape, spacing = (3, 3, (1 << 24) + 1), (1e-3, 1e-3, 1e-3)
+    rng = np.random.default_rng(6950)
+    z = np.arange(shape[2], dtype=np.float64)
+    T = np.empty(shape)
+    T[:] = 37.0 + 600.0 * np.exp(-((z - 0.5 * shape[2]) / 40.0) ** 2)
+    T[1] += 3.0
+    T[:, 1] += 1.5
+    v = np.zeros((3,) + shape, np.float32)
+    v[2] = rng.uniform(-3e-3, 3e-3, shape).astype(np.float32)
+    v[0] = rng.uniform(-0.4e-3, 0.4e-3, shape).astype(np.float32)
+    g = _grid(shape, spacing)
+    g.set_temperature(T)
+    out = g.warp(v, 0.8)
+    ref = warp_oracle(T, v, spacing, 0.8)
+    err = np.abs(out.astype(np.float64) - ref).max()
+    print("long rows max err", err)
+    assert err <= GATE
+    del ref
+    hi, lo = g.raw_state()
+    assert np.array_equal(g.warp(v, 0.0), rounded_state(hi, lo))
+    g.close()
+
+
 def test_warp_rejects_bad_arguments():
     from paper_1907_05709_amd import rfa
     shape = (6, 7, 8)
