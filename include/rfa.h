@@ -233,9 +233,14 @@ rfa_status rfa_set_temperature(rfa_grid g, const double* t_C);
 
 /* Breathing-motion view of the current temperature (Eq. (eq:breathing)):
  * out[x] = T(x + beta v(x)) in degC, T taken trilinearly between voxel
- * centres from the float-float temperature state (sample positions in FP64,
- * the interpolant rounded once to float: within 1e-4 K of the exact
- * interpolant), sample positions beyond the grid taken on its walls.  v: [3][nx*ny*nz] float, the
+ * centres from the temperature state, sample positions beyond the grid
+ * taken on its walls.  Accuracy: within 1e-4 K of the exact interpolant of
+ * the float-float state (sample positions formed as float-float pairs; the
+ * lo words of the state enter in cells with a corner at or above 1024 degC,
+ * elsewhere they are below half an ulp of the hi word; the result rounded
+ * once to float).  A sample exactly on a voxel centre (zero displacement,
+ * integer shifts, positions clamped to a wall) is that voxel's float-float
+ * state rounded once.  v: [3][nx*ny*nz] float, the
  * x, y and z components of the inverse breathing displacement in metres;
  * beta: the breathing surrogate (finite); out: [nx*ny*nz] float, caller
  * owned.  v and out are host or device pointers per inputs_on_device; on
@@ -250,8 +255,8 @@ rfa_status rfa_warp(rfa_grid g, const float* v, double beta, float* out, double*
  * beta1 v1(x) + beta2 v2(x): the keyframe form of the motion model (two
  * consecutive phase fields weighted 1 - a and a) or a regression on two
  * surrogate signals (Sec. "Consideration of Breathing Motion").  v1, v2 as v
- * above (v2 required); the position beta1 v1 + beta2 v2 is one FP64 fused
- * multiply-add on top of beta1 v1, so beta2 = 0 gives exactly
+ * above (v2 required); beta2 v2 is added to the float-float position
+ * beta1 v1 by an exact two-sum, so beta2 = 0 gives exactly
  * rfa_warp(v1, beta1).
  * Errors as rfa_warp. */
 rfa_status rfa_warp2(rfa_grid g, const float* v1, double beta1, const float* v2, double beta2,
