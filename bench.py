@@ -203,6 +203,14 @@ def roofline_dict(bytes_per_launch, avg_ms, kernel, **extra):
     return r
 
 
+def mix_ceiling(roof: dict, mix_gbps: float) -> dict:
+    """The streaming rate of the step's byte mix without its stencil at the
+    same size (rfa_mix_bandwidth), measured in the same run, and the
+    kernel's achieved rate as a fraction of it."""
+    return {"mix_ceiling_GBps": round(mix_gbps, 1),
+            "frac_of_mix_ceiling": round(roof["achieved"] / mix_gbps, 4)}
+
+
 def run_single(config: int, steps: int, warmup: int, plan_arg: str = "", tune: bool = False,
                time_steps: int = 0, cpu: bool = True, cpu_steps: int = 0) -> dict:
     """One grid stepped by its whole duration per bench step (configs 2, 3,
@@ -234,6 +242,7 @@ def run_single(config: int, steps: int, warmup: int, plan_arg: str = "", tune: b
     kms, launches, _ = g.kernel_stats()
     support = g.source_support()
     copy_gbps = rfa.rfa_copy_bandwidth(1 << 30, 10)
+    mix_gbps = rfa.rfa_mix_bandwidth(case.n_voxels, 10)
     g.close()
 
     value = case.n_voxels * case.n_steps * steps / wall / 1e9
@@ -241,6 +250,7 @@ def run_single(config: int, steps: int, warmup: int, plan_arg: str = "", tune: b
     roof = roofline_dict(BYTES_PER_VOXEL_STEP * case.n_voxels + SOURCE_BYTES * support, avg_ms,
                          kernel_name(plan), launches_timed=launches,
                          copy_ceiling_GBps=round(copy_gbps, 1), source_support_voxels=support)
+    roof.update(mix_ceiling(roof, mix_gbps))
     roof["traffic"] = traffic_record(config, plan, kernel_name(plan))
     # working set of one step: state in and out, class, source, damage
     ws_mb = case.n_voxels * (16 + 1 + 4 + 4) / 1e6
@@ -391,12 +401,15 @@ def bench_batch(args) -> dict:
     b.close()
     for g in grids:
         g.close()
+    mix_gbps = rfa.rfa_mix_bandwidth(total_vox // plan["groups"], 10)
     roof = roofline_dict(bytes_per_launch, avg_launch_ms, "k_step_batch",
                          launches_timed=launches, copy_ceiling_GBps=round(copy_gbps, 1),
                          source_support_voxels=support,
                          note="groups of grids sized to the 256 MB last-level cache run "
                               "their steps back to back; traffic counts bytes below L2, "
-                              "which that cache may serve")
+                              "which that cache may serve; the mix ceiling is taken over "
+                              "one average group's voxels")
+    roof.update(mix_ceiling(roof, mix_gbps))
     roof["traffic"] = traffic_record(4, plan, "k_step_batch")
     out = {
         "value": round(value, 3),

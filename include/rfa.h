@@ -312,6 +312,16 @@ rfa_status rfa_tune(rfa_grid g, double dt, int reps);
  * (read + write counted), GB/s: the achievable HBM ceiling on this device. */
 rfa_status rfa_copy_bandwidth(size_t bytes, int reps, double* gbps);
 
+/* Measured streaming rate of the step kernels' byte mix without their
+ * stencil, GB/s: per voxel theta hi and lo, the class byte and Omega read,
+ * theta and Omega written (25 B, counted as such), over n_voxels voxels
+ * (>= 4096; rounded up to a multiple of 4) in two image sets used in turn,
+ * reps passes, the fastest of four launch widths.  The ceiling a step
+ * kernel of that grid size could reach; n_voxels * 25 B of device memory
+ * is allocated for the call.  Errors: RFA_ERR_ARG (arguments),
+ * RFA_ERR_OOM / RFA_ERR_HIP (device). */
+rfa_status rfa_mix_bandwidth(long long n_voxels, int reps, double* gbps);
+
 /* ---- Differentiation -------------------------------------------------------
  * The damage integral after N steps, Omega^N (Eq. (eq-tissState) summed by
  * the stepper), is a differentiable function of the tine powers and of the

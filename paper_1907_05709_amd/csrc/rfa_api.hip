@@ -1358,6 +1358,54 @@ rfa_status rfa_copy_bandwidth(size_t bytes, int reps, double* gbps) {
   return RFA_OK;
 }
 
+rfa_status rfa_mix_bandwidth(long long n_voxels, int reps, double* gbps) {
+  if (!gbps || n_voxels < 4096 || reps < 1)
+    return fail(RFA_ERR_ARG, "n_voxels >= 4096, reps >= 1");
+  const size_t n4 = ((size_t)n_voxels + 3) / 4;
+  float4* buf[6] = {};
+  unsigned* lab = nullptr;
+  rfa_status s = RFA_OK;
+  for (int k = 0; k < 6 && s == RFA_OK; ++k) s = dmalloc(&buf[k], n4);
+  if (s == RFA_OK) s = dmalloc(&lab, n4);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipSuccess;
+  float best_ms = 1e30f;
+  if (s == RFA_OK) {
+    for (int k = 0; k < 3 && e == hipSuccess; ++k)
+      e = hipMemsetAsync(buf[k], 0, n4 * sizeof(float4), nullptr);
+    if (e == hipSuccess) e = hipMemsetAsync(lab, 0, n4 * sizeof(unsigned), nullptr);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const float4* const ping_in[3] = {buf[0], buf[1], buf[2]};
+    float4* const ping_out[3] = {buf[3], buf[4], buf[5]};
+    const float4* const pong_in[3] = {buf[3], buf[4], buf[5]};
+    float4* const pong_out[3] = {buf[0], buf[1], buf[2]};
+    // a few launch widths; the fastest is the ceiling.  Passes alternate
+    // between the two image sets, as the stepper's do.
+    for (int blocks : {2048, 4096, 8192, 16384}) {
+      float ms = 0.f;
+      if (e == hipSuccess) e = launch_stream_mix(ping_in, lab, ping_out, n4, blocks, nullptr);
+      if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+      for (int r = 0; r < reps && e == hipSuccess; ++r)
+        e = (r & 1) ? launch_stream_mix(pong_in, lab, pong_out, n4, blocks, nullptr)
+                    : launch_stream_mix(ping_in, lab, ping_out, n4, blocks, nullptr);
+      if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess) best_ms = std::min(best_ms, ms);
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (float4* b : buf)
+    if (b) (void)hipFree(b);
+  if (lab) (void)hipFree(lab);
+  if (s != RFA_OK) return s;
+  if (e != hipSuccess) return fail(RFA_ERR_HIP, "mix bandwidth: %s", hipGetErrorString(e));
+  *gbps = 25.0 * (double)(4 * n4) * reps / (best_ms * 1e-3) / 1e9;
+  return RFA_OK;
+}
+
 // ---- differentiation ----------------------------------------------------------------
 rfa_status rfa_set_perfusion_bspline(rfa_grid g, int m, const float* ctrl) {
   if (!g || !ctrl) return fail(RFA_ERR_ARG, "grid and ctrl are required");

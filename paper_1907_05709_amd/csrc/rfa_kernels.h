@@ -136,6 +136,10 @@ hipError_t launch_count_flag(Grid3 g, const uint8_t* lab, unsigned flag,
 // p[0 .. n) = 0 (one small work-group; graph-capturable, unlike a memset).
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
 // Plain streaming copy b = a of n4 float4 (bandwidth ceiling probe).
+// Streaming probe of the step's 25 B/voxel mix: in = {hi, lo, omega},
+// out likewise, lab one 32-bit word per four voxels; n4 float4 per array.
+hipError_t launch_stream_mix(const float4* const (&in)[3], const unsigned* lab,
+                             float4* const (&out)[3], size_t n4, int blocks, hipStream_t st);
 hipError_t launch_copy(const float4* a, float4* b, size_t n4, hipStream_t st);
 // The same with non-temporal hints and four float4 per thread per pass.
 hipError_t launch_copy_nt(const float4* a, float4* b, size_t n4, hipStream_t st);

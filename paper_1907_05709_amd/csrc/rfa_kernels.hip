@@ -693,6 +693,34 @@ hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Streaming probe of the step kernels' byte mix without the stencil: per
+// voxel read theta hi and lo, the class byte and Omega, write theta hi, lo
+// and Omega (25 B), four voxels per thread as 16-byte accesses.  The
+// arithmetic only keeps every load live.
+__global__ __launch_bounds__(256) void k_stream_mix(const float4* __restrict__ hi,
+                                                    const float4* __restrict__ lo,
+                                                    const unsigned* __restrict__ lab,
+                                                    const float4* __restrict__ om,
+                                                    float4* __restrict__ hi_o,
+                                                    float4* __restrict__ lo_o,
+                                                    float4* __restrict__ om_o, size_t n4) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const float s = (float)(lab[i] & 0xffu) * 1e-30f;
+    const float4 h = hi[i], l = lo[i], o = om[i];
+    hi_o[i] = make_float4(h.x + s, h.y + s, h.z + s, h.w + s);
+    lo_o[i] = make_float4(l.x - s, l.y - s, l.z - s, l.w - s);
+    om_o[i] = make_float4(o.x + s, o.y + s, o.z + s, o.w + s);
+  }
+}
+
+hipError_t launch_stream_mix(const float4* const (&in)[3], const unsigned* lab,
+                             float4* const (&out)[3], size_t n4, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_stream_mix, dim3((unsigned)blocks), dim3(256), 0, st, in[0], in[1], lab,
+                     in[2], out[0], out[1], out[2], n4);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ a,
                                               float4* __restrict__ b, size_t n4) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;

@@ -86,6 +86,7 @@ _SIGS = {
     "rfa_get_plan": [C.c_void_p] + [C.POINTER(C.c_int)] * 6,
     "rfa_tune": [C.c_void_p, C.c_double, C.c_int],
     "rfa_copy_bandwidth": [C.c_size_t, C.c_int, C.POINTER(C.c_double)],
+    "rfa_mix_bandwidth": [C.c_longlong, C.c_int, C.POINTER(C.c_double)],
     "rfa_adjoint_kernel_stats": [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
     "rfa_warp": [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.POINTER(C.c_double)],
     "rfa_warp2": [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_double, C.c_void_p,
@@ -309,6 +310,13 @@ def rfa_adjoint_kernel_stats(g):
 def rfa_copy_bandwidth(nbytes: int, reps: int = 20) -> float:
     v = C.c_double()
     _check(lib().rfa_copy_bandwidth(int(nbytes), int(reps), C.byref(v)))
+    return v.value
+
+
+def rfa_mix_bandwidth(n_voxels: int, reps: int = 10) -> float:
+    """Streaming rate (GB/s) of the step's 25 B/voxel mix without the stencil."""
+    v = C.c_double()
+    _check(lib().rfa_mix_bandwidth(int(n_voxels), int(reps), C.byref(v)))
     return v.value
 
 

@@ -332,6 +332,20 @@ def test_tune_keeps_state_and_timing_counts_launches():
     g.close()
 
 
+def test_stream_mix_probe():
+    """The streaming probe of the step's byte mix: a positive rate below
+    the peak times the cache's reuse, odd voxel counts rounded up, bad
+    arguments refused."""
+    from paper_1907_05709_amd import rfa
+    for n in (4096, (1 << 22) + 3):
+        r = rfa.rfa_mix_bandwidth(n, 3)
+        assert 10.0 < r < 1e5, (n, r)
+    for bad in ((4095, 3), (1 << 20, 0)):
+        with pytest.raises(rfa.RfaError) as e:
+            rfa.rfa_mix_bandwidth(*bad)
+        assert e.value.status == rfa.RFA_ERR_ARG
+
+
 def test_arrhenius_constant_temperature_gpu():
     """Held tissue voxel at 60 degC: Omega = n dt A exp(-Ea/(R T_K))."""
     case = W.case_homogeneous(n=8, n_steps=400, dt=0.01)
