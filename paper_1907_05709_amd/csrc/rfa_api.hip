@@ -146,6 +146,11 @@ struct rfa_grid_s {
 
   // step-kernel timing
   std::vector<hipEvent_t> events;
+  // second stream of the checkpointed adjoint (segment recomputes run on it
+  // while the adjoint steps of the next later segment run on st) and its
+  // ordering events: start, recompute done [2], adjoint done [2]
+  hipStream_t side = nullptr;
+  hipEvent_t side_ev[5] = {};
   double kernel_ms = 0.0;
   long long kernel_launches = 0;
   long long kernel_voxel_steps = 0;
@@ -189,6 +194,13 @@ void free_all(rfa_grid g) {
   f(g->lab_scratch);
   for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
   g->events.clear();
+  for (hipEvent_t& e : g->side_ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
+  if (g->side) (void)hipStreamSynchronize(g->side);
+  if (g->side) (void)hipStreamDestroy(g->side);
+  g->side = nullptr;
 }
 
 template <class T>
@@ -419,6 +431,15 @@ rfa_status ensure_events(rfa_grid g, int count) {
     HIP_TRY(hipEventCreate(&e));
     g->events.push_back(e);
   }
+  return RFA_OK;
+}
+
+// The adjoint's second stream (default priority, not blocking on the null
+// stream) and its ordering events, created on first use.
+rfa_status ensure_side_stream(rfa_grid g) {
+  if (!g->side) HIP_TRY(hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking));
+  for (hipEvent_t& e : g->side_ev)
+    if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   return RFA_OK;
 }
 
@@ -1590,7 +1611,10 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
   const size_t n = g->g.n();
   const int every = g->adj_every;  // 0: the forward kept the whole trajectory
   rfa_status s;
-  const size_t tneed = (size_t)(every + 1) * n;
+  // two halves of (every + 1) hi images: segment seg is recomputed into
+  // half seg & 1 while the adjoint steps read the other half
+  const size_t seg_floats = (size_t)(every + 1) * n;
+  const size_t tneed = 2 * seg_floats;
   if (every > 0 && g->traj_floats < tneed) {
     if (g->traj) (void)hipFree(g->traj);
     g->traj = nullptr;
@@ -1667,27 +1691,51 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
       g->adj_kernel_launches += g->adj_steps;
     }
   }
-  for (int seg = g->adj_nckpt - 1; seg >= 0; --seg) {
-    const int k = std::min(every, g->adj_steps - seg * every);
-    const float* c = g->ckpt + (size_t)seg * 2 * n;
-    HIP_TRY(hipMemcpyAsync(g->traj, c, n * sizeof(float), hipMemcpyDeviceToDevice, g->st));
-    HIP_TRY(hipMemcpyAsync(lopp[0], c + n, n * sizeof(float), hipMemcpyDeviceToDevice, g->st));
-    for (int t = 0; t < k; ++t) {  // recompute theta^t of the segment (bitwise as forward)
-      StepBuffers b;
-      b.hi_in = g->traj + (size_t)t * n;
-      b.lo_in = lopp[t & 1];
-      b.hi_out = g->traj + (size_t)(t + 1) * n;
-      b.lo_out = lopp[(t + 1) & 1];
-      b.lab = g->lab_scratch;
-      b.src = g->src;
-      b.omega = om_s;
-      b.perf = g->perf;
-      b.tab = g->tab_dev;
-      b.partials = nullptr;
-      b.n_classes = g->n_classes;
-      HIP_TRY(launch_plan(g->g, plan_one(g->plan), b, K, g->st));
+  // Checkpointed: segments from the last one back.  The recompute of a
+  // segment (from its checkpoint, bitwise as the forward) runs on the side
+  // stream into one half of traj while the adjoint steps of the later
+  // segment read the other half on the grid's stream; events order each
+  // half's reuse.  The recompute writes only traj, the lo ping-pong, the
+  // scratch class bytes and damage integral, none of which the adjoint reads
+  // but traj.
+  if (every > 0) {
+    if ((s = ensure_side_stream(g)) != RFA_OK) return s;
+    hipEvent_t start = g->side_ev[0];
+    hipEvent_t ready[2] = {g->side_ev[1], g->side_ev[2]};
+    hipEvent_t read[2] = {g->side_ev[3], g->side_ev[4]};
+    bool used[2] = {false, false};
+    HIP_TRY(hipEventRecord(start, g->st));
+    HIP_TRY(hipStreamWaitEvent(g->side, start, 0));
+    for (int seg = g->adj_nckpt - 1; seg >= 0; --seg) {
+      const int k = std::min(every, g->adj_steps - seg * every);
+      const int half = seg & 1;
+      float* traj = g->traj + (size_t)half * seg_floats;
+      const float* c = g->ckpt + (size_t)seg * 2 * n;
+      if (used[half]) HIP_TRY(hipStreamWaitEvent(g->side, read[half], 0));
+      HIP_TRY(hipMemcpyAsync(traj, c, n * sizeof(float), hipMemcpyDeviceToDevice, g->side));
+      HIP_TRY(
+          hipMemcpyAsync(lopp[0], c + n, n * sizeof(float), hipMemcpyDeviceToDevice, g->side));
+      for (int t = 0; t < k; ++t) {
+        StepBuffers b;
+        b.hi_in = traj + (size_t)t * n;
+        b.lo_in = lopp[t & 1];
+        b.hi_out = traj + (size_t)(t + 1) * n;
+        b.lo_out = lopp[(t + 1) & 1];
+        b.lab = g->lab_scratch;
+        b.src = g->src;
+        b.omega = om_s;
+        b.perf = g->perf;
+        b.tab = g->tab_dev;
+        b.partials = nullptr;
+        b.n_classes = g->n_classes;
+        HIP_TRY(launch_plan(g->g, plan_one(g->plan), b, K, g->side));
+      }
+      HIP_TRY(hipEventRecord(ready[half], g->side));
+      HIP_TRY(hipStreamWaitEvent(g->st, ready[half], 0));
+      for (int t = k - 1; t >= 0; --t) HIP_TRY(adjoint_step(traj + (size_t)t * n));
+      HIP_TRY(hipEventRecord(read[half], g->st));
+      used[half] = true;
     }
-    for (int t = k - 1; t >= 0; --t) HIP_TRY(adjoint_step(g->traj + (size_t)t * n));
   }
   if (dL_dP) {
     const int nt = (int)g->power.size();

@@ -6,8 +6,12 @@
 // index, so a wave covers 64 consecutive z voxels and, the motion being
 // smooth, its corner gathers fall on a few contiguous cache lines of four
 // source rows.  Bytes that must move per voxel: the three displacement
-// components, one output, and the float-float source state once (24 bytes);
-// the 2 x 2 corner re-reads are served by the caches.
+// components, one output and the state's hi word once (20 bytes; lo words
+// only where they matter, see kLoAll); the 2 x 2 corner re-reads are served
+// by the caches.  What bounds the kernel is the gathers themselves: each
+// corner gather instruction costs about the same whatever its width or
+// whether its lanes are masked out by offset, so the kernel issues as few
+// as the accuracy allows.
 //
 // Accuracy (the view is within 1e-4 K of the FP64 interpolant of the state):
 //  * sample positions are float-float: the displacement in voxels is up to
