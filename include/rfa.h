@@ -361,7 +361,12 @@ rfa_status rfa_forward_checkpointed(rfa_grid g, int n_steps, double dt, int ckpt
  * (float, [nx*ny*nz], memory space per inputs_on_device).  Outputs, each
  * nullable: dL_dP[n_tines] (host, W^-1), dL_dctrl[m^3] (host; requires
  * rfa_set_perfusion_bspline), dL_dperf[nx*ny*nz] = dL/df per voxel (float,
- * memory space per inputs_on_device). */
+ * memory space per inputs_on_device).  With checkpoints, each segment is
+ * recomputed on a second stream owned by the grid, into one half of a
+ * double buffer of (ckpt_every + 1) images, while the adjoint steps of the
+ * later segment run on the grid's stream; events order the two, so all of
+ * the call's work stays ordered after earlier and before later work on the
+ * grid's stream. */
 rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* dL_dctrl,
                        float* dL_dperf);
 
