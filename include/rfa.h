@@ -316,7 +316,7 @@ rfa_status rfa_copy_bandwidth(size_t bytes, int reps, double* gbps);
  * stencil, GB/s: per voxel theta hi and lo, the class byte and Omega read,
  * theta and Omega written (25 B, counted as such), over n_voxels voxels
  * (>= 4096; rounded up to a multiple of 4) in two image sets used in turn,
- * reps passes, the fastest of four launch widths.  The ceiling a step
+ * reps passes, the fastest of five launch widths.  The ceiling a step
  * kernel of that grid size could reach; n_voxels * 25 B of device memory
  * is allocated for the call.  Errors: RFA_ERR_ARG (arguments),
  * RFA_ERR_OOM / RFA_ERR_HIP (device). */

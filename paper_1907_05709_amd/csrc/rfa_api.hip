@@ -1352,10 +1352,14 @@ rfa_status rfa_copy_bandwidth(size_t bytes, int reps, double* gbps) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipSuccess;
   float best_ms = 1e30f;
-  // two copy kernels (plain, non-temporal x4); the faster one is the ceiling
-  for (int variant = 0; variant < 2 && e == hipSuccess; ++variant) {
+  // the plain copy at three launch widths (a grid-stride loop over 1024
+  // work-groups streams best on MI355X) and the non-temporal x4 copy; the
+  // fastest is the ceiling
+  const int widths[3] = {1024, 4096, 16384};
+  for (int variant = 0; variant < 4 && e == hipSuccess; ++variant) {
     auto launch = [&]() {
-      return variant == 0 ? launch_copy(a, b, n4, nullptr) : launch_copy_nt(a, b, n4, nullptr);
+      return variant < 3 ? launch_copy(a, b, n4, widths[variant], nullptr)
+                         : launch_copy_nt(a, b, n4, nullptr);
     };
     float ms = 0.f;
     do {
@@ -1403,7 +1407,7 @@ rfa_status rfa_mix_bandwidth(long long n_voxels, int reps, double* gbps) {
     float4* const pong_out[3] = {buf[0], buf[1], buf[2]};
     // a few launch widths; the fastest is the ceiling.  Passes alternate
     // between the two image sets, as the stepper's do.
-    for (int blocks : {2048, 4096, 8192, 16384}) {
+    for (int blocks : {1024, 2048, 4096, 8192, 16384}) {
       float ms = 0.f;
       if (e == hipSuccess) e = launch_stream_mix(ping_in, lab, ping_out, n4, blocks, nullptr);
       if (e == hipSuccess) e = hipEventRecord(e0, nullptr);

@@ -140,7 +140,7 @@ hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
 // out likewise, lab one 32-bit word per four voxels; n4 float4 per array.
 hipError_t launch_stream_mix(const float4* const (&in)[3], const unsigned* lab,
                              float4* const (&out)[3], size_t n4, int blocks, hipStream_t st);
-hipError_t launch_copy(const float4* a, float4* b, size_t n4, hipStream_t st);
+hipError_t launch_copy(const float4* a, float4* b, size_t n4, int max_blocks, hipStream_t st);
 // The same with non-temporal hints and four float4 per thread per pass.
 hipError_t launch_copy_nt(const float4* a, float4* b, size_t n4, hipStream_t st);
 // Free voxels per class [16].

@@ -750,8 +750,8 @@ __global__ __launch_bounds__(256) void k_copy_nt(const float4* __restrict__ a4,
   for (; i < n4; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(a + i), b + i);
 }
 
-hipError_t launch_copy(const float4* a, float4* b, size_t n4, hipStream_t st) {
-  const size_t blocks = std::min<size_t>((n4 + 255) / 256, 256 * 64);
+hipError_t launch_copy(const float4* a, float4* b, size_t n4, int max_blocks, hipStream_t st) {
+  const size_t blocks = std::min<size_t>((n4 + 255) / 256, (size_t)max_blocks);
   hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, a, b, n4);
   return hipGetLastError();
 }
