@@ -184,12 +184,17 @@ def test_tiled_kernel_bitwise_equals_reference(shape, ty, xc):
                                               ((21, 45, 64), 8, 7, False),
                                               ((64, 64, 62), 8, 64, True),
                                               ((5, 66, 131), 16, 4, False),
-                                              ((9, 5, 3), 8, 4, False)])
+                                              ((9, 5, 3), 8, 4, False),
+                                              ((40, 37, 70), 8, 6, False),
+                                              ((33, 70, 129), 16, 14, True),
+                                              ((62, 20, 40), 8, 30, False)])
 def test_two_step_kernel_bitwise_equals_reference(shape, ty, xc, perf):
     """Temporal blocking (two steps per launch, overlapped halo) against the
     one-thread-per-voxel reference: identical states, damage and latches
     after odd and even step counts (an odd count ends with one single
-    step), with and without a perfusion field, on ragged tiles."""
+    step), with and without a perfusion field, on ragged tiles, with chunk
+    lengths of 2 mod 4 planes (the four-plane march then makes no pass
+    outside the chunk) and others."""
     from paper_1907_05709_amd import rfa
     case = W.random_tissue_case(70 + ty + xc, shape=shape, n_classes=5, n_tines=2, n_steps=40)
     field = None
