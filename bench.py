@@ -472,7 +472,7 @@ def bench_adjoint(args, steps: int, warmup: int) -> dict:
     def one_step(every):
         g.reset_state()
         g.forward_checkpointed(n_steps, case.dt, every)
-        _, om, _ = g.damage()
+        om = g.omega()
         om.requires_grad_(True)
         loss = coverage_loss(om, labels, vox)
         (w,) = torch.autograd.grad(loss, om)

@@ -202,7 +202,8 @@ rfa_status rfa_dt_max(rfa_grid g, double* dt_max);
  * = per class dead volume by bit0 then by bit1, m^3 (the ablation zone of
  * Sec. "Results").  mask [nx*ny*nz] u8 and omega [nx*ny*nz] are caller
  * owned, host or device per inputs_on_device; dead_m3 is host memory.  Host
- * outputs synchronise the grid's stream. */
+ * outputs synchronise the grid's stream; device outputs with dead_m3 = NULL
+ * are only enqueued on it. */
 rfa_status rfa_damage(rfa_grid g, uint8_t* mask, float* omega, double* dead_m3);
 
 /* rfa_damage for callers that cannot allocate device memory (code under
@@ -353,7 +354,10 @@ rfa_status rfa_set_tine_powers(rfa_grid g, const double* power);
  * temperature (hi word) of every step when ckpt_every = 0 (one step per
  * launch, written straight into the kept trajectory; RFA_ERR_OOM if it does
  * not fit: use checkpoints), else the state at steps 0, ckpt_every,
- * 2 ckpt_every, ... */
+ * 2 ckpt_every, ... plus the hi word of every step of the last segment,
+ * written into the adjoint's segment buffer (2 (ckpt_every + 1) images,
+ * allocated here), so the first rfa_adjoint after it recomputes every
+ * segment but the last. */
 rfa_status rfa_forward_checkpointed(rfa_grid g, int n_steps, double dt, int ckpt_every);
 
 /* Adjoint of the last rfa_forward_checkpointed (the grid must not have

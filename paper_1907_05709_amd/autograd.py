@@ -28,7 +28,7 @@ class RfaFunction(torch.autograd.Function):
         grid.set_perfusion_bspline(ctrl.detach().float().cpu().numpy())
         grid.reset_state()
         grid.forward_checkpointed(int(n_steps), float(dt), int(ckpt_every))
-        _, omega, _ = grid.damage()
+        omega = grid.omega()
         ctx.grid = grid
         ctx.n_tines = int(powers.numel())
         ctx.m = int(ctrl.shape[0])
@@ -53,10 +53,11 @@ def coverage_loss(omega, labels, voxel_m3: float, tumour: int = 2, liver: int = 
     # sigmoid(4 ln Omega) written without the logarithm (Omega may be 0)
     d = 1.0 / (1.0 + torch.where(om > 0, om, torch.ones_like(om)).pow(-4.0))
     d = torch.where(om > 0, d, torch.zeros_like(d))
-    tum = labels == tumour
-    liv = labels == liver
-    u = (1.0 - d[tum]).mean() if bool(tum.any()) else d.sum() * 0.0
-    dv = d[liv].sum() * (voxel_m3 * 1e6)
+    # masked sums rather than boolean indexing: no device-to-host sync
+    tum = (labels == tumour).double()
+    liv = (labels == liver).double()
+    u = ((1.0 - d) * tum).sum() / tum.sum().clamp_min(1.0)  # 0 without tumour voxels
+    dv = (d * liv).sum() * (voxel_m3 * 1e6)
     return u + healthy_weight * dv
 
 

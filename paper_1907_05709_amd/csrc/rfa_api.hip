@@ -119,6 +119,7 @@ struct rfa_grid_s {
   bool adj_ready = false;
   int adj_version = 0;
   int adj_steps = 0, adj_every = 0, adj_nckpt = 0;
+  bool adj_tail_kept = false;      // traj holds the last segment's hi images (see rfa_adjoint)
   double adj_dt = 0.0;
   float* ckpt = nullptr;           // [nckpt][2][N] hi, lo at segment starts
   size_t ckpt_floats = 0;
@@ -951,16 +952,21 @@ rfa_status rfa_damage(rfa_grid g, uint8_t* mask, float* omega, double* dead_m3) 
   }
   hipError_t e = hipSuccess;
   unsigned long long cnt[2 * kMaxClasses] = {};
+  // the mask kernel (which also counts) runs only for a mask or dead
+  // volumes; only host outputs make the call synchronise
+  const bool host_out = dead_m3 || ((mask || omega) && !g->opt.inputs_on_device);
   do {
-    if ((e = hipMemsetAsync(g->counts, 0, sizeof cnt, g->st)) != hipSuccess) break;
-    if ((e = launch_damage(g->g, g->lab, g->om, dmask, g->counts, g->st)) != hipSuccess) break;
+    if (mask || dead_m3) {
+      if ((e = hipMemsetAsync(g->counts, 0, sizeof cnt, g->st)) != hipSuccess) break;
+      if ((e = launch_damage(g->g, g->lab, g->om, dmask, g->counts, g->st)) != hipSuccess) break;
+    }
     if (mask && !g->opt.inputs_on_device &&
         (e = hipMemcpyAsync(mask, dmask, n, hipMemcpyDeviceToHost, g->st)) != hipSuccess) break;
     if (omega && (e = hipMemcpyAsync(omega, g->om, n * sizeof(float), kind_out(g), g->st)) !=
                      hipSuccess) break;
-    if ((e = hipMemcpyAsync(cnt, g->counts, sizeof cnt, hipMemcpyDeviceToHost, g->st)) !=
-        hipSuccess) break;
-    if ((e = hipStreamSynchronize(g->st)) != hipSuccess) break;
+    if (dead_m3 && (e = hipMemcpyAsync(cnt, g->counts, sizeof cnt, hipMemcpyDeviceToHost,
+                                       g->st)) != hipSuccess) break;
+    if (host_out && (e = hipStreamSynchronize(g->st)) != hipSuccess) break;
   } while (false);
   if (dmask && dmask != mask) (void)hipFree(dmask);
   if (e != hipSuccess) return fail(RFA_ERR_HIP, "damage failed: %s", hipGetErrorString(e));
@@ -1567,6 +1573,7 @@ rfa_status rfa_forward_checkpointed(rfa_grid g, int n_steps, double dt, int ckpt
     g->adj_steps = n_steps;
     g->adj_every = 0;
     g->adj_nckpt = 0;
+    g->adj_tail_kept = false;
     g->adj_dt = dt;
     return RFA_OK;
   }
@@ -1580,7 +1587,18 @@ rfa_status rfa_forward_checkpointed(rfa_grid g, int n_steps, double dt, int ckpt
     if ((s = dmalloc(&g->ckpt, need)) != RFA_OK) return s;
     g->ckpt_floats = need;
   }
+  // the adjoint's two segment buffers; the last segment's hi images go
+  // straight into its buffer, so the adjoint starts without a recompute
+  const size_t seg_floats = (size_t)(every + 1) * n;
+  if (g->traj_floats < 2 * seg_floats) {
+    if (g->traj) (void)hipFree(g->traj);
+    g->traj = nullptr;
+    g->traj_floats = 0;
+    if ((s = dmalloc(&g->traj, 2 * seg_floats)) != RFA_OK) return s;
+    g->traj_floats = 2 * seg_floats;
+  }
   g->adj_ready = false;
+  g->adj_tail_kept = false;
   const StepConst K = step_const(g, dt);
   for (int seg = 0; seg < nck; ++seg) {
     float* c = g->ckpt + (size_t)seg * 2 * n;
@@ -1588,8 +1606,19 @@ rfa_status rfa_forward_checkpointed(rfa_grid g, int n_steps, double dt, int ckpt
     HIP_TRY(hipMemcpyAsync(c + n, g->lo[g->cur], n * sizeof(float), hipMemcpyDeviceToDevice,
                            g->st));
     const int k = std::min(every, n_steps - seg * every);
-    if ((s = timed_steps(g, K, k, false)) != RFA_OK) return s;
+    if (seg < nck - 1) {
+      if ((s = timed_steps(g, K, k, false)) != RFA_OK) return s;
+      continue;
+    }
+    float* traj = g->traj + (size_t)(seg & 1) * seg_floats;
+    HIP_TRY(hipMemcpyAsync(traj, g->hi[g->cur], n * sizeof(float), hipMemcpyDeviceToDevice,
+                           g->st));
+    int t = 0;
+    if ((s = timed_steps(g, K, k, false, traj, &t)) != RFA_OK) return s;
+    HIP_TRY(hipMemcpyAsync(g->hi[g->cur], traj + (size_t)k * n, n * sizeof(float),
+                           hipMemcpyDeviceToDevice, g->st));
   }
+  g->adj_tail_kept = true;
   g->energy_valid = false;
   ++g->version;
   g->adj_ready = true;
@@ -1623,6 +1652,7 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
     if (g->traj) (void)hipFree(g->traj);
     g->traj = nullptr;
     g->traj_floats = 0;
+    g->adj_tail_kept = false;
     if ((s = dmalloc(&g->traj, tneed)) != RFA_OK) return s;
     g->traj_floats = tneed;
   }
@@ -1715,6 +1745,13 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
       const int half = seg & 1;
       float* traj = g->traj + (size_t)half * seg_floats;
       const float* c = g->ckpt + (size_t)seg * 2 * n;
+      if (seg == g->adj_nckpt - 1 && g->adj_tail_kept) {
+        // written by the forward itself: no recompute
+        for (int t = k - 1; t >= 0; --t) HIP_TRY(adjoint_step(traj + (size_t)t * n));
+        HIP_TRY(hipEventRecord(read[half], g->st));
+        used[half] = true;
+        continue;
+      }
       if (used[half]) HIP_TRY(hipStreamWaitEvent(g->side, read[half], 0));
       HIP_TRY(hipMemcpyAsync(traj, c, n * sizeof(float), hipMemcpyDeviceToDevice, g->side));
       HIP_TRY(
@@ -1740,6 +1777,9 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
       HIP_TRY(hipEventRecord(read[half], g->st));
       used[half] = true;
     }
+    // later segments may have overwritten the kept one: a second adjoint
+    // of this forward recomputes every segment
+    g->adj_tail_kept = false;
   }
   if (dL_dP) {
     const int nt = (int)g->power.size();

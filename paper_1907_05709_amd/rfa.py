@@ -574,6 +574,13 @@ class Grid:
                    _ptr(om, self.device, np.float32, True), C.c_void_p(dead.ctypes.data))
         return mask, om, dead.reshape(-1, 2)
 
+    def omega(self):
+        """The damage integral alone (rfa_damage with the other outputs NULL:
+        for a device grid no synchronisation)."""
+        om = self._alloc(np.float32)
+        rfa_damage(self.h, None, _ptr(om, self.device, np.float32, True), None)
+        return om
+
     def damage_noalloc(self, want_mask: bool = True, want_omega: bool = True,
                        want_dead: bool = True):
         """rfa_damage_noalloc: as damage(), through the allocation-free entry

@@ -213,6 +213,11 @@ def test_checkpoint_spacing_does_not_change_gradients(setup):
         _, om, _ = g.damage()
         _, w = coverage(case, om)
         out.append(g.adjoint(w.astype(np.float32), len(P), M, want_dperf=True))
+        # the forward writes the last segment's trajectory itself; a second
+        # adjoint of the same forward recomputes that segment too
+        again = g.adjoint(w.astype(np.float32), len(P), M, want_dperf=True)
+        for a, b in zip(out[-1], again):
+            assert np.array_equal(a, b)
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
     for a, b in zip(out[0], out[2]):

@@ -401,3 +401,22 @@ def test_source_flags_follow_the_source():
     assert g.source_support() == 0
     g.close()
     ref.close()
+
+
+@pytest.mark.parametrize("device", [False, True])
+def test_omega_read_alone_equals_damage_output(device):
+    """rfa_damage with only the damage integral asked for (no mask kernel;
+    for a device grid no synchronisation) gives damage()'s integral bit for
+    bit, and later calls see the grid as before."""
+    case = W.random_tissue_case(61, shape=(21, 17, 33), n_classes=5, n_tines=2, n_steps=80)
+    g, T, mask, om, dead, d = parity.gpu_run(case, device=device)
+    om2 = g.omega()
+    if device:
+        om2 = om2.cpu().numpy()
+    assert np.array_equal(om, om2)
+    assert om.max() > 0
+    mask3, om3, dead3 = g.damage()
+    if device:
+        mask3, om3 = mask3.cpu().numpy(), om3.cpu().numpy()
+    assert np.array_equal(mask, mask3) and np.array_equal(om, om3) and np.array_equal(dead, dead3)
+    g.close()
