@@ -1729,9 +1729,11 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
   // segment (from its checkpoint, bitwise as the forward) runs on the side
   // stream into one half of traj while the adjoint steps of the later
   // segment read the other half on the grid's stream; events order each
-  // half's reuse.  The recompute writes only traj, the lo ping-pong, the
-  // scratch class bytes and damage integral, none of which the adjoint reads
-  // but traj.
+  // half's reuse.  The recompute reproduces only the temperature (the
+  // adjoint refuses damage-coupled perfusion, so nothing else feeds it): it
+  // writes traj and the lo ping-pong, and with kernels other than the wide
+  // one also the scratch class bytes and damage integral, none of which the
+  // adjoint reads.
   if (every > 0) {
     if ((s = ensure_side_stream(g)) != RFA_OK) return s;
     hipEvent_t start = g->side_ev[0];
@@ -1769,7 +1771,7 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
         b.tab = g->tab_dev;
         b.partials = nullptr;
         b.n_classes = g->n_classes;
-        HIP_TRY(launch_plan(g->g, plan_one(g->plan), b, K, g->side));
+        HIP_TRY(launch_plan_temperature(g->g, plan_one(g->plan), b, K, g->side));
       }
       HIP_TRY(hipEventRecord(ready[half], g->side));
       HIP_TRY(hipStreamWaitEvent(g->st, ready[half], 0));

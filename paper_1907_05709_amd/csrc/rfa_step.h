@@ -63,6 +63,11 @@ struct StepState {
 // One launch of the plan (plan.depth steps) from b's input to its output image.
 hipError_t launch_plan(Grid3 g, const StepPlan& plan, const StepBuffers& b, const StepConst& K,
                        hipStream_t st);
+// One step of a one-step plan where only the temperature must come out
+// right (no damage-coupled perfusion): the wide kernel then skips the damage
+// integral and the class bytes; other plans run their full step.
+hipError_t launch_plan_temperature(Grid3 g, const StepPlan& plan, const StepBuffers& b,
+                                   const StepConst& K, hipStream_t st);
 
 // Advance n_steps: n_steps / depth launches of the plan, then the rest with
 // its one-step plan.  partials (nullable) has room for `slots` launches and

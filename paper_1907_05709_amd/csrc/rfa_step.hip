@@ -195,6 +195,14 @@ hipError_t launch_plan(Grid3 g, const StepPlan& plan, const StepBuffers& b, cons
   return launch_step_tiled(tiled_shape(g, plan.ty, plan.xc), g, b, K, plan.store, st);
 }
 
+hipError_t launch_plan_temperature(Grid3 g, const StepPlan& plan, const StepBuffers& b,
+                                   const StepConst& K, hipStream_t st) {
+  if (plan.kind != kStepNaive && plan.depth == 1 && plan.zv > 1)
+    return launch_step_wide_temperature(plan.zv, wide_shape(g, plan.zv, plan.ty, plan.xc), g, b,
+                                        K, plan.store, st);
+  return launch_plan(g, plan, b, K, st);
+}
+
 rfa_status run_steps(Grid3 g, const StepPlan& plan, StepState& s, const StepConst& K,
                      int n_steps, float* partials, int slots, double* dacc, hipEvent_t* events,
                      int period, int* n_timed, int* n_launches, hipStream_t st) {

@@ -67,6 +67,12 @@ TiledShape wide_shape(Grid3 g, int zv, int ty, int xc);
 bool wide_fits(Grid3 g, int zv, int xc);
 hipError_t launch_step_wide(int zv, const TiledShape& s, Grid3 g, const StepBuffers& b,
                             const StepConst& K, int store, hipStream_t st);
+// The same step writing only the temperature (hi, lo): the damage integral
+// and class bytes are neither read nor written.  Valid without
+// damage-coupled perfusion, where the temperature does not depend on them.
+hipError_t launch_step_wide_temperature(int zv, const TiledShape& s, Grid3 g,
+                                        const StepBuffers& b, const StepConst& K, int store,
+                                        hipStream_t st);
 
 // Two steps per launch (temporal blocking, ty = 8 or 16): tiles own
 // 62 x (ty - 2) columns and recompute a one-voxel rim of the first step.

@@ -27,6 +27,13 @@
 //
 // The per-voxel arithmetic is voxel_step() of rfa_device.h, so results are
 // bitwise those of the other step kernels.
+//
+// TONLY (temperature only): without damage-coupled perfusion the new
+// temperature depends on neither the damage integral nor the latch bit, so
+// a launch that must reproduce only the temperature (the adjoint's segment
+// recompute) skips the damage integral's load and store and the class-byte
+// store: 21 instead of 29 bytes per voxel-step with a perfusion field, the
+// temperature bitwise that of a full step.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -130,7 +137,7 @@ struct WideSmem {
 // field (and its damage coupling) they would spill there and run three
 // waves per SIMD instead; four voxels per lane keep the compiler's choice
 // (two waves per SIMD).
-template <int ZV, int TY, bool PERF, int AUX>
+template <int ZV, int TY, bool PERF, int AUX, bool TONLY>
 __global__ __launch_bounds__(64 * TY, ZV == 2 ? (PERF ? 3 : 4) : 1) void k_step_wide(StepBuffers b, StepConst K, int nx,
                                                        int ny, int nz, int xc, int tiles_z,
                                                        int tiles_y, int nwg) {
@@ -200,7 +207,10 @@ __global__ __launch_bounds__(64 * TY, ZV == 2 ? (PERF ? 3 : 4) : 1) void k_step_
     q.h = ldv<ZV>(r_hi, col * 4, so4);
     q.l = ldv<ZV>(r_lo, col * 4, so4);
     q.b = ldb<ZV>(r_lab, col, so1);
-    q.om = ldv<ZV>(r_om, col * 4, sf4);
+    if constexpr (TONLY)
+      q.om = VF{};
+    else
+      q.om = ldv<ZV>(r_om, col * 4, sf4);
     if constexpr (PERF) q.pf = ldv<ZV>(r_pf, col * 4, sf4);
     q.hh = ldv<ZV>(r_hi, hoff4, sf4);
     q.hl = ldv<ZV>(r_lo, hoff4, sf4);
@@ -295,9 +305,11 @@ __global__ __launch_bounds__(64 * TY, ZV == 2 ? (PERF ? 3 : 4) : 1) void k_step_
       const unsigned v4 = valid ? st4 + 4u * (unsigned)so : kOob;
       stv<ZV, AUX>(nh, r_hio, v4);
       stv<ZV, AUX>(nl, r_loo, v4);
-      stv<ZV, AUX>(om, r_om, v4);
-      // past the chunk the computed bytes carry the held flag: never stored
-      stb<ZV, AUX>(nlab, r_lab, (valid && nlab != P.b) ? st1 : kOob, so);
+      if constexpr (!TONLY) {
+        stv<ZV, AUX>(om, r_om, v4);
+        // past the chunk the computed bytes carry the held flag: never stored
+        stb<ZV, AUX>(nlab, r_lab, (valid && nlab != P.b) ? st1 : kOob, so);
+      }
     }
     hm = P.h;
     lm = P.l;
@@ -336,37 +348,49 @@ bool wide_fits(Grid3 g, int zv, int xc) {
          (double)(xc + 2) * g.ny * g.nz * 4.0 < 2147483647.0;
 }
 
-template <int ZV, int TY, int AUX>
+template <int ZV, int TY, int AUX, bool TONLY>
 static hipError_t launch_wide_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
                                  const StepConst& K, hipStream_t st) {
   dim3 grid(s.nwg), block(64 * TY);
   if (b.perf)
-    hipLaunchKernelGGL((k_step_wide<ZV, TY, true, AUX>), grid, block, 0, st, b, K, g.nx, g.ny,
-                       g.nz, s.xc, s.tiles_z, s.tiles_y, s.nwg);
+    hipLaunchKernelGGL((k_step_wide<ZV, TY, true, AUX, TONLY>), grid, block, 0, st, b, K, g.nx,
+                       g.ny, g.nz, s.xc, s.tiles_z, s.tiles_y, s.nwg);
   else
-    hipLaunchKernelGGL((k_step_wide<ZV, TY, false, AUX>), grid, block, 0, st, b, K, g.nx, g.ny,
-                       g.nz, s.xc, s.tiles_z, s.tiles_y, s.nwg);
+    hipLaunchKernelGGL((k_step_wide<ZV, TY, false, AUX, TONLY>), grid, block, 0, st, b, K, g.nx,
+                       g.ny, g.nz, s.xc, s.tiles_z, s.tiles_y, s.nwg);
   return hipGetLastError();
 }
 
-template <int ZV, int TY>
+template <int ZV, int TY, bool TONLY>
 static hipError_t launch_wide_ty(const TiledShape& s, Grid3 g, const StepBuffers& b,
                                  const StepConst& K, int store, hipStream_t st) {
   switch (store) {
-    case kPolicyThrough: return launch_wide_ty<ZV, TY, kStoreThrough>(s, g, b, K, st);
-    case kPolicyStream: return launch_wide_ty<ZV, TY, kStoreStream>(s, g, b, K, st);
-    default: return launch_wide_ty<ZV, TY, kStoreBack>(s, g, b, K, st);
+    case kPolicyThrough: return launch_wide_ty<ZV, TY, kStoreThrough, TONLY>(s, g, b, K, st);
+    case kPolicyStream: return launch_wide_ty<ZV, TY, kStoreStream, TONLY>(s, g, b, K, st);
+    default: return launch_wide_ty<ZV, TY, kStoreBack, TONLY>(s, g, b, K, st);
   }
+}
+
+template <bool TONLY>
+static hipError_t launch_wide(int zv, const TiledShape& s, Grid3 g, const StepBuffers& b,
+                              const StepConst& K, int store, hipStream_t st) {
+  if (!wide_fits(g, zv, s.xc)) return hipErrorInvalidValue;
+  if (zv == 4 && s.ty == 4) return launch_wide_ty<4, 4, TONLY>(s, g, b, K, store, st);
+  if (zv == 4 && s.ty == 8) return launch_wide_ty<4, 8, TONLY>(s, g, b, K, store, st);
+  if (zv == 2 && s.ty == 4) return launch_wide_ty<2, 4, TONLY>(s, g, b, K, store, st);
+  if (zv == 2 && s.ty == 8) return launch_wide_ty<2, 8, TONLY>(s, g, b, K, store, st);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_step_wide(int zv, const TiledShape& s, Grid3 g, const StepBuffers& b,
                             const StepConst& K, int store, hipStream_t st) {
-  if (!wide_fits(g, zv, s.xc)) return hipErrorInvalidValue;
-  if (zv == 4 && s.ty == 4) return launch_wide_ty<4, 4>(s, g, b, K, store, st);
-  if (zv == 4 && s.ty == 8) return launch_wide_ty<4, 8>(s, g, b, K, store, st);
-  if (zv == 2 && s.ty == 4) return launch_wide_ty<2, 4>(s, g, b, K, store, st);
-  if (zv == 2 && s.ty == 8) return launch_wide_ty<2, 8>(s, g, b, K, store, st);
-  return hipErrorInvalidValue;
+  return launch_wide<false>(zv, s, g, b, K, store, st);
+}
+
+hipError_t launch_step_wide_temperature(int zv, const TiledShape& s, Grid3 g,
+                                        const StepBuffers& b, const StepConst& K, int store,
+                                        hipStream_t st) {
+  return launch_wide<true>(zv, s, g, b, K, store, st);
 }
 
 }  // namespace rfa

@@ -64,9 +64,9 @@ def setup():
     return case, ctrl
 
 
-def gpu_grid(case, ctrl):
+def gpu_grid(case, ctrl, **plan):
     from paper_1907_05709_amd import rfa
-    g = rfa.Grid(case.shape, case.spacing)
+    g = rfa.Grid(case.shape, case.spacing, **plan)
     g.load_case(case)
     g.set_perfusion_bspline(ctrl)
     return g
@@ -201,9 +201,14 @@ def test_tiled_adjoint_bitwise_equals_reference(shape):
     assert np.array_equal(dP1, dP2) and np.array_equal(f1, f2)
 
 
-def test_checkpoint_spacing_does_not_change_gradients(setup):
+# the automatic plan, and the wide kernel (two z voxels per lane), whose
+# recompute steps skip the damage integral and class bytes
+@pytest.mark.parametrize("plan", [{}, dict(z_vec=2, tile_y=4, tile_x=8)])
+def test_checkpoint_spacing_does_not_change_gradients(setup, plan):
     case, ctrl = setup
-    g = gpu_grid(case, ctrl)
+    g = gpu_grid(case, ctrl, **plan)
+    if plan:
+        assert g.plan()["z_vec"] == 2 and g.plan()["depth"] == 1
     P = case.needle.power.copy()
     g.set_tine_powers(P)
     out = []
