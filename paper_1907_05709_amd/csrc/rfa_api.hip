@@ -1676,12 +1676,17 @@ rfa_status rfa_adjoint(rfa_grid g, const float* w_omega, double* dL_dP, double* 
   // adjoint schedule: the tiled kernel (8 rows, x chunks sized for about
   // one work-group per compute unit; at 128^3: 256 work-groups of 16 planes,
   // 8 % faster than 1024 work-groups of 4 rows x 8 planes) unless the grid
-  // asked for the reference kernels
+  // asked for the reference kernels.  Beside the segment recomputes (which
+  // leave each compute unit fewer free cycles) two work-groups per compute
+  // unit of half the length finish sooner: 512 work-groups of 8 planes at
+  // 128^3 (the recompute-and-adjoint phase 5 % shorter; alone both widths
+  // take the same time)
   constexpr int adj_ty = 8;
   int adj_xc = 4;
   {
+    const int target = every > 0 ? 512 : 256;
     const int tiles = ((g->g.nz + 63) / 64) * ((g->g.ny + adj_ty - 1) / adj_ty);
-    const int chunks = std::max(1, (256 + tiles - 1) / tiles);
+    const int chunks = std::max(1, (target + tiles - 1) / tiles);
     adj_xc = std::min(g->g.nx, std::max(4, (g->g.nx + chunks - 1) / chunks));
   }
   const bool tiled_adj = g->plan.kind != kStepNaive && adjoint_tiled_fits(g->g, adj_xc);
