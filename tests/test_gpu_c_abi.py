@@ -1,7 +1,9 @@
 """The C ABI on its own: a plain C99 program (c_abi_driver.c), built with gcc
 against include/rfa.h and librfa.so, with no Python, ctypes or torch in the
-process, steps a seeded case and its outputs are held to the same parity
-rules against the FP64 oracle as the binding's."""
+process, steps a seeded case (outputs held to the same parity rules against
+the FP64 oracle as the binding's), batches copies of it (bitwise equal to a
+copy stepped alone) and differentiates it (gradients bitwise those of the
+binding on the same case)."""
 from __future__ import annotations
 
 import math
@@ -102,6 +104,51 @@ def test_c_program_matches_oracle(seed, shape, tmp_path):
     assert math.isclose(d["energy_J"], dg[-1, 0], rel_tol=2e-5)
     scale = abs(dg[:, 1].sum()) + abs(dg[:, 2].sum()) + abs(dg[:, 3].sum())
     assert abs(d["residual_J"]) <= 1e-6 * scale
+
+
+@pytest.mark.gpu
+def test_c_program_batches_grids(tmp_path):
+    """rfa_batch_create / rfa_batch_step / rfa_batch_get_plan /
+    rfa_batch_destroy from C: two copies of a case stepped in one batch end
+    bitwise equal to a third stepped alone."""
+    exe = _build(tmp_path)
+    case = W.random_tissue_case(45, shape=(30, 22, 41), n_classes=4, n_tines=2, n_steps=37)
+    _write_case(tmp_path / "case.bin", case)
+    r = subprocess.run([exe, str(tmp_path / "case.bin"), str(tmp_path / "out.bin"), "batch"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    print(r.stdout.strip())
+    equal, layout, tile_y, tile_x, items, workgroups, groups = struct.unpack(
+        "<7i", open(tmp_path / "out.bin", "rb").read())
+    assert equal == 1
+    assert layout in (rfa.RFA_BATCH_TILES, rfa.RFA_BATCH_FLAT) and items > 0 and groups >= 1
+
+
+@pytest.mark.gpu
+def test_c_program_adjoint_equals_binding(tmp_path):
+    """rfa_set_perfusion_bspline / rfa_forward_checkpointed / rfa_adjoint
+    from C give the binding's gradients bit for bit on the same case."""
+    exe = _build(tmp_path)
+    case = W.random_tissue_case(46, shape=(20, 18, 24), n_classes=4, n_tines=3, n_steps=40)
+    _write_case(tmp_path / "case.bin", case)
+    r = subprocess.run([exe, str(tmp_path / "case.bin"), str(tmp_path / "out.bin"), "adjoint"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    print(r.stdout.strip())
+    nt = len(case.needle.power)
+    raw = open(tmp_path / "out.bin", "rb").read()
+    assert len(raw) == 8 * (nt + 64)
+    dP_c = np.frombuffer(raw, "<f8", nt, 0)
+    dc_c = np.frombuffer(raw, "<f8", 64, 8 * nt).reshape(4, 4, 4)
+    g = rfa.Grid(case.shape, case.spacing, t_death=case.t_death, A=case.arrhenius_a,
+                 Ea=case.arrhenius_ea, R=case.gas_r, omega_cap=case.omega_cap)
+    g.load_case(case)
+    g.set_perfusion_bspline(np.zeros((4, 4, 4), np.float32))
+    g.forward_checkpointed(case.n_steps, case.dt, case.n_steps // 3 + 1)
+    dP, dc, _ = g.adjoint(np.ones(case.shape, np.float32), nt, 4)
+    g.close()
+    assert np.abs(dP).max() > 0
+    assert np.array_equal(dP, dP_c) and np.array_equal(dc, dc_c)
 
 
 @pytest.mark.gpu
